@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark: batched SUR GLS solves/s, mixed precision vs plain FP64 PCG-Aug.
+
+Workload: 512 independent SUR instances (G ~ U{4..32}, M ~ U{500..5000},
+n_i ~ U{3..20}, K = 16 right-hand sides each; X_i intercept + N(0,1),
+Omega = A A^T + 0.1 I), seeded synthetic data drawn on the host and resident
+in HBM before timing.  One step = factor (batched Householder QR) + solve of
+all 8,192 (instance, rhs) pairs.  `value` is the mixed-precision throughput;
+the FP64 path is timed on the same inputs and both are checked against the
+CPU oracle on a sample of instances at <= 1e-10 relative error.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SUR GLS solves/s: batched mixed-prec vs plain FP64 PCG at ≤1e-10 rel err"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    import numpy as np
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--tol", type=float, default=1e-12)
+    ap.add_argument("--check", type=int, default=12, help="instances checked against the oracle")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the batched solver has no multi-GPU path in "
+              "this build (instances would shard across GPUs without communication); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2510_14471_amd as glm
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t0 = time.time()
+    batch = synth.config2(B=args.instances)
+    insts = list(batch)
+    log(f"generated {len(insts)} instances in {time.time() - t0:.1f}s")
+    lay, d = glm.pack_instances(insts)
+    torch.cuda.synchronize()
+    n_solves = lay.n_rhs
+    log(f"packed: X {d['X'].numel() * 8 / 1e9:.2f} GB, y {d['y'].numel() * 8 / 1e9:.2f} GB")
+
+    def timed(solver, steps, profile=False):
+        if profile:
+            solver.profile(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        iters = 0
+        outer = 0
+        for _ in range(steps):
+            solver.factor(d["X"])
+            beta, u, _, info, _ = solver.solve(d["Omega"], d["y"], tol=args.tol)
+            st = solver.stats()
+            iters += st["pcg_iterations"]
+            outer += st["outer_steps"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        prof = None
+        if profile:
+            prof = {k: solver.profile_read(k) for k in (0, 1)}
+            solver.profile(False)
+        return dt, iters, outer, beta, u, info, prof
+
+    results = {}
+    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+        s = glm.SURSolver(lay, prec)
+        log(f"{prec}: workspace {s.workspace_bytes / 1e9:.2f} GB")
+        for _ in range(args.warmup):
+            timed(s, 1)
+        dt, iters, outer, beta, u, info, prof = timed(s, args.steps, profile=(prec == "mixed"))
+        infos = info.cpu().numpy()
+        results[prec] = dict(dt=dt, iters=iters, outer=outer, beta=beta, u=u,
+                             ok=int(np.sum((infos == 0) | (infos == 1))), prof=prof)
+        log(f"{prec}: {args.steps} steps in {dt:.3f}s -> {n_solves * args.steps / dt:.1f} solves/s,"
+            f" {iters / args.steps:.0f} PCG iterations/step, outer {outer / args.steps:.1f},"
+            f" ok {results[prec]['ok']}/{n_solves}")
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+
+    # accuracy against the oracle on a sample of instances
+    from oracle import gls as ogls
+    errs = {}
+    sample = list(range(0, len(insts), max(1, len(insts) // max(1, args.check))))[: args.check]
+    for prec, r in results.items():
+        betas = glm.unpack(lay, r["beta"], "beta")
+        us = glm.unpack(lay, r["u"], "u")
+        eb = eu = 0.0
+        for b in sample:
+            beta_o, U_o = ogls.sur_gls(insts[b])
+            for k in range(insts[b].K):
+                eb = max(eb, rel(betas[b][:, k], beta_o[:, k]))
+                eu = max(eu, rel(us[b][:, :, k], U_o[:, :, k]))
+        errs[prec] = (eb, eu)
+        log(f"{prec}: max rel err on {len(sample)} instances: beta {eb:.2e}, u {eu:.2e}")
+
+    mixed = results["mixed"]
+    value = n_solves * args.steps / mixed["dt"]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000 * mixed["dt"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"sur_batch{len(insts)}_K16: G~U{{4..32}}, M~U{{500..5000}}, "
+                               "n_i~U{3..20}, Omega=AA^T+0.1I; step = QR factor + mixed "
+                               "solve of all (instance, rhs)",
+                   "instances": len(insts), "solves_per_step": n_solves, "tol": args.tol},
+        "pcg_iterations_per_s": round(mixed["iters"] / mixed["dt"], 1),
+        "outer_steps": round(mixed["outer"] / args.steps, 2),
+        "max_rel_err": {p: {"beta": e[0], "u": e[1]} for p, e in errs.items()},
+        "converged": {p: f"{r['ok']}/{n_solves}" for p, r in results.items()},
+    }
+    if "fp64" in results:
+        f64 = results["fp64"]
+        v64 = n_solves * args.steps / f64["dt"]
+        out["fp64_solves_per_s"] = round(v64, 2)
+        out["speedup_mixed_vs_fp64"] = round(value / v64, 3)
+        out["fp64_pcg_iterations_per_s"] = round(f64["iters"] / f64["dt"], 1)
+    prof = mixed["prof"]
+    if prof:
+        kid = max((0, 1), key=lambda k: prof[k][1])
+        n_l, ms, by = prof[kid]
+        names = {0: "k_pass_a<float> (u <- g + mu u, Sigma u, d, Q^T Sigma u)",
+                 1: "k_pass_b<float> (Sigma u - Q T, g, w updates, c)"}
+        ach = (by / n_l) / (ms / n_l * 1e-3) / 1e9 if n_l and ms > 0 else 0.0
+        out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                           "traffic": None, "kernel": names[kid], "launches": n_l,
+                           "avg_us": round(1000 * ms / max(n_l, 1), 2),
+                           "alg_bytes_per_launch": round(by / max(n_l, 1))}
+        other = 1 - kid
+        n2, ms2, by2 = prof[other]
+        if n2:
+            out["roofline_other"] = {"kernel": names[other], "avg_us": round(1000 * ms2 / n2, 2),
+                                     "achieved": round((by2 / n2) / (ms2 / n2 * 1e-3) / 1e9, 1)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(insts, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(insts, budget_s):
+    """The oracle (textbook SUR GLS by Cholesky, NumPy/LAPACK) on the host cores,
+    on the first instances of the same workload until ~budget_s of work."""
+    import numpy as np
+    from oracle import gls as ogls
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    t = time.perf_counter()
+    solves = 0
+    done = 0
+    for inst in insts:
+        ogls.sur_gls(inst)
+        solves += inst.K
+        done += 1
+        if time.perf_counter() - t > budget_s:
+            break
+    dt = time.perf_counter() - t
+    return {"value": round(solves / dt, 2), "unit": "solves/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"first {done} of {len(insts)} instances ({solves} solves), {dt:.1f}s"}
+
+
+if __name__ == "__main__":
+    main()

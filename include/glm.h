@@ -1,0 +1,224 @@
+/*
+ * glm.h -- C ABI of the gfx950 PCG-Aug solver for SUR generalized least squares.
+ *
+ * The method (Foschi, "Preconditioned Conjugate Gradient methods for the
+ * estimation of General Linear Models"):
+ *   - a SUR model  y = vec(Y),  X = X_1 (+) ... (+) X_G,  Sigma = Omega (x) I_M
+ *     (SUR section, eq. SURdefs), optionally with linear restrictions
+ *     R_c beta = r (restricted GLM section, eq. RGLM);
+ *   - the GLS estimate is the beta-block of the augmented system
+ *       [Sigma X; X^T 0] [u; beta] = [y; 0]                       (eq. aug1)
+ *     which stays well posed for a singular PSD Omega as long as Sigma is
+ *     positive definite on the null space of X^T (eq. SigmaPosXNull) or y is
+ *     consistent;
+ *   - the system is solved by preconditioned conjugate gradients with the
+ *     indefinite preconditioner K = [D X; X^T 0]^-1 (eq. invprec, eq. prec),
+ *     D = alpha I with alpha = max_i omega_ii, whose application is one OLS
+ *     step per equation through thin QR factors X_i = Q_i R_i (Algorithm
+ *     "The PCG-Aug method"; SUR section).
+ *
+ * Conventions shared by every entry point
+ *   - A batch holds B independent instances.  Instance b has G_b equations,
+ *     M_b observations, K_b right-hand sides (1 <= K_b <= 16), k_b restriction
+ *     rows (0 = unrestricted) and columns n_{b,1..G_b}; n_b = sum_i n_{b,i}.
+ *   - Every batched array is the concatenation, in instance order, of the
+ *     per-instance arrays below (no gaps, no per-instance offsets):
+ *        X      M_b x n_b     row-major, the blocks side by side [X_1 ... X_G]
+ *        Rc     k_b x n_b     row-major (instances with k_b = 0 contribute nothing)
+ *        Omega  G_b x G_b     row-major, symmetric positive semi-definite
+ *        y, u   M_b x G_b x K_b   row-major: element (t, i, k) = observation t
+ *                                 of equation i for right-hand side k
+ *        r, uc  k_b x K_b     row-major
+ *        beta   n_b x K_b     row-major, blocks stacked in equation order
+ *   - All array arguments are DEVICE pointers (HBM of the current device)
+ *     unless marked "host".  Double precision throughout the interface.
+ *   - Every call enqueues its work on `stream`.  glm_qr_factor does not
+ *     block the host.  glm_gls_solve and glm_gls_backward block the calling
+ *     thread while they iterate (they poll convergence flags every few
+ *     iterations) and return once all results are written.
+ *   - Nothing throws across the boundary and nothing calls exit/abort.
+ *     Host-detectable problems return a negative code immediately, before
+ *     any work is enqueued; device-detected conditions are reported per
+ *     (instance, right-hand side) in `info`.
+ *   - The library never allocates or frees device memory: the caller
+ *     provides one workspace (size from glm_workspace_bytes) that holds the
+ *     factors, the iteration vectors and all partial sums.  It allocates a
+ *     small pinned host buffer per factor handle for convergence polling.
+ *   - A handle and its workspace serve one call at a time.
+ */
+#ifndef GLM_H
+#define GLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes --------------------------------------------------------- */
+#define GLM_OK             0
+#define GLM_EINVAL        -1   /* bad shape, NULL where required, K outside 1..16 */
+#define GLM_EWORKSPACE    -2   /* workspace too small or NULL                   */
+#define GLM_EHIP          -3   /* a HIP runtime call failed                     */
+#define GLM_EUNSUPPORTED  -4   /* valid request outside what this build handles */
+
+/* ---- per (instance, right-hand side) outcome written to `info` ------------- */
+#define GLM_INFO_CONVERGED   0  /* stopping test met                                   */
+#define GLM_INFO_STAGNATED   1  /* c_i stopped decreasing (terminated, as the paper
+                                   allows, at the attainable accuracy)                */
+#define GLM_INFO_NOCONV    -10  /* iteration limit reached; outputs hold the last
+                                   iterate                                             */
+#define GLM_INFO_BREAKDOWN -11  /* d_i <= 0 or not finite; outputs hold beta recovered
+                                   from the current u (Algorithm PCG-Aug, termination) */
+#define GLM_INFO_RANK      -12  /* an X_i (or [X; R_c]) is numerically rank deficient;
+                                   nothing was solved for this instance               */
+
+typedef enum glm_precision {
+  GLM_FP64 = 0,   /* every step in double precision                               */
+  GLM_MIXED = 1   /* inner PCG with single-precision Q_i, vectors and Omega
+                     (single-precision accumulation, double-precision dot
+                     products), inside double-precision iterative refinement;
+                     QR, refinement residual and the beta/u updates in double   */
+} glm_precision;
+
+typedef struct glm_shape {
+  int32_t batch;          /* B >= 1                                               */
+  const int32_t* G;       /* host [B]   G_b >= 1                                  */
+  const int32_t* M;       /* host [B]   M_b >= 1                                  */
+  const int32_t* K;       /* host [B]   1 <= K_b <= 16                            */
+  const int32_t* k;       /* host [B]   restriction rows k_b >= 0, or NULL (all 0) */
+  const int32_t* n;       /* host [sum_b G_b]  1 <= n_{b,i} <= M_b, instance-major */
+} glm_shape;
+
+typedef struct glm_factor glm_factor;   /* opaque host handle */
+
+/* Aggregate counters of the last solve/backward on a handle (host struct). */
+typedef struct glm_stats {
+  int32_t outer_steps;        /* refinement steps (1 for GLM_FP64)                */
+  int64_t pcg_iterations;     /* sum over (instance, rhs) of PCG iterations       */
+  int32_t max_iterations;     /* largest per-(instance, rhs) PCG iteration count  */
+  int32_t launches;           /* kernel launches enqueued by the call            */
+} glm_stats;
+
+/* Bytes of device workspace needed by glm_qr_factor / glm_gls_solve /
+ * glm_gls_backward for this shape and precision.  Returns 0 for an invalid
+ * shape (see glm_validate_shape for the reason). */
+size_t glm_workspace_bytes(const glm_shape* shape, glm_precision prec);
+
+/* Checks a shape without touching the device.  Returns GLM_OK, GLM_EINVAL or
+ * GLM_EUNSUPPORTED (e.g. n_b too large for K_b, see the limits in the
+ * implementation notes). */
+int glm_validate_shape(const glm_shape* shape);
+
+/* Factors every block once (SUR section: the data matrices are fixed, so
+ * they are factorised only once): batched Householder QR X_i = Q_i R_i in
+ * double precision, the explicit thin Q_i (plus a single-precision copy for
+ * GLM_MIXED), the column-to-block maps and the tile schedule of the
+ * iteration kernels.  With restrictions it also builds an orthonormal basis
+ * N of the null space of [R; R_c]^T, which turns the OLS step of the
+ * restricted problem (eq. rglm1m) into the unrestricted one plus a rank-k
+ * correction.
+ *
+ *   X    device, M_b x n_b per instance (see conventions); must stay valid
+ *        and unmodified while the handle is used (the refinement residual of
+ *        GLM_MIXED reads X in double precision)
+ *   Rc   device, k_b x n_b per restricted instance, or NULL if all k_b = 0;
+ *        same lifetime rule as X
+ *   ws   device workspace of ws_bytes >= glm_workspace_bytes(shape, prec),
+ *        owned by the caller, outliving the handle
+ *   out  host: receives the new handle (release with glm_factor_destroy)
+ * Rank deficiency of a block is detected on the device and reported by the
+ * next solve as GLM_INFO_RANK.  Returns GLM_OK or a negative code. */
+int glm_qr_factor(const glm_shape* shape, glm_precision prec,
+                  const double* X, const double* Rc,
+                  void* ws, size_t ws_bytes, hipStream_t stream,
+                  glm_factor** out);
+
+/* Solves every (instance, rhs) of the batch with PCG-Aug (projected form:
+ * the iteration carries g_i = Pi r_i and one OLS projection per step).
+ *
+ *   Omega     device, G_b x G_b per instance, symmetric PSD (may be singular:
+ *             then y must be consistent, e.g. generated by the model)
+ *   y         device, M_b x G_b x K_b per instance
+ *   r         device, k_b x K_b per restricted instance, or NULL if none
+ *   tol       GLM_FP64: stop when sqrt(c_i / c_1) <= tol (c_i = r_i^T Pi r_i);
+ *             GLM_MIXED: stop when the double-precision residual of eq. aug1,
+ *             ||[y - Sigma u - X beta ; -X^T u]|| <= tol * ||y||
+ *   max_iter  PCG iteration limit per (instance, rhs) (per inner solve for
+ *             GLM_MIXED); <= 0 selects m - n + 1 (Algorithm PCG-Aug bound)
+ *   beta      device out, n_b x K_b per instance
+ *   u         device out, M_b x G_b x K_b per instance: the u-block of the
+ *             augmented solution (Sigma u = y - X beta, X^T u = 0); unique
+ *             only for nonsingular Omega
+ *   uc        device out, k_b x K_b per restricted instance (the u-block rows
+ *             of the restrictions, i.e. their multipliers), or NULL
+ *   info      device out, int32 per (instance, rhs) in batch order: GLM_INFO_*
+ *   iters     device out, int32 per (instance, rhs): PCG iterations (total
+ *             inner iterations for GLM_MIXED), or NULL
+ * Returns GLM_OK or a negative code. */
+int glm_gls_solve(glm_factor* f, const double* Omega, const double* y,
+                  const double* r, double tol, int32_t max_iter,
+                  double* beta, double* u, double* uc,
+                  int32_t* info, int32_t* iters, hipStream_t stream);
+
+/* Reverse mode of glm_gls_solve (same handle, same Omega, outputs of the
+ * forward solve).  The augmented matrix A = [Sigma X; X^T 0] is symmetric, so
+ * the adjoint solve  A [l_u; l_beta] = [g_u; g_beta]  reuses the factors; then
+ *   dy      = l_u
+ *   dOmega  = -sym( sum_{t,k} l_u[t,:,k] u[t,:,k]^T )   (symmetric gradient:
+ *             dL = <dOmega, E> for every symmetric perturbation E)
+ *   dX_i    = -sum_k ( l_u,i beta_i^T + u_i l_beta,i^T )
+ * Defined for nonsingular Omega.  Restricted instances are solved in the
+ * restricted geometry (gradients w.r.t. R_c and r are not produced).
+ *
+ *   beta, u   device, the forward outputs
+ *   g_beta    device, n_b x K_b per instance (dL/dbeta)
+ *   g_u       device, M_b x G_b x K_b per instance (dL/du), or NULL (zero)
+ *   dy        device out, M_b x G_b x K_b per instance
+ *   dOmega    device out, G_b x G_b per instance, or NULL
+ *   dX        device out, M_b x n_b per instance, or NULL
+ *   info, iters   as for glm_gls_solve (for the adjoint solve)
+ * Returns GLM_OK or a negative code. */
+int glm_gls_backward(glm_factor* f, const double* Omega,
+                     const double* beta, const double* u,
+                     const double* g_beta, const double* g_u,
+                     double tol, int32_t max_iter,
+                     double* dy, double* dOmega, double* dX,
+                     int32_t* info, int32_t* iters, hipStream_t stream);
+
+/* Copies the factors out of the workspace (enqueued on `stream`):
+ *   Q      device out, M_b x n_b per instance, laid out like X (may be NULL)
+ *   R      device out, the R_i (n_i x n_i, row-major, upper triangular) of every
+ *          block in batch order (may be NULL)
+ *   rank   device out, int32 per block: 1 if the block was found numerically
+ *          rank deficient (may be NULL)
+ * The signs of the rows of R_i (and columns of Q_i) follow the Householder
+ * convention (R_jj may be negative).  GLM_OK or GLM_EINVAL / GLM_EHIP. */
+int glm_copy_factors(const glm_factor* f, double* Q, double* R, int32_t* rank,
+                     hipStream_t stream);
+
+/* Counters of the last solve/backward on the handle.  GLM_OK or GLM_EINVAL. */
+int glm_get_stats(const glm_factor* f, glm_stats* out);
+
+/* Kernel timing for measurement.  While enabled, every launch of the two
+ * OLS-projection pass kernels is bracketed by HIP events on the launch stream
+ * and its algorithmic bytes are counted on the device (tiles of inactive
+ * instances count nothing).  glm_profile_read synchronises the stream and
+ * returns, for kernel id 0 (projection pass A) and 1 (projection pass B),
+ * the number of launches, their summed duration in milliseconds and the
+ * summed algorithmic bytes; it then clears the counters. */
+int glm_profile_enable(glm_factor* f, int on);
+int glm_profile_read(glm_factor* f, int kernel_id, int64_t* launches,
+                     double* total_ms, double* total_bytes);
+
+void glm_factor_destroy(glm_factor* f);
+
+/* Static description of a return or info code; never NULL. */
+const char* glm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLM_H */

@@ -1,0 +1,193 @@
+"""ctypes binding of include/glm.h.
+
+Functions keep the C names and only marshal arguments: torch tensors become
+device pointers, Python sequences become host int32 arrays.  Every numeric
+step runs in the HIP library; if the library is missing the import of this
+module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libglm_hip.so")
+
+GLM_FP64 = 0
+GLM_MIXED = 1
+
+GLM_OK = 0
+GLM_EINVAL = -1
+GLM_EWORKSPACE = -2
+GLM_EHIP = -3
+GLM_EUNSUPPORTED = -4
+GLM_INFO_CONVERGED = 0
+GLM_INFO_STAGNATED = 1
+GLM_INFO_NOCONV = -10
+GLM_INFO_BREAKDOWN = -11
+GLM_INFO_RANK = -12
+
+PRECISIONS = {"fp64": GLM_FP64, "mixed": GLM_MIXED}
+
+
+class GlmShape(ctypes.Structure):
+    _fields_ = [("batch", c_int32), ("G", POINTER(c_int32)), ("M", POINTER(c_int32)),
+                ("K", POINTER(c_int32)), ("k", POINTER(c_int32)), ("n", POINTER(c_int32))]
+
+
+class GlmStats(ctypes.Structure):
+    _fields_ = [("outer_steps", c_int32), ("pcg_iterations", c_int64),
+                ("max_iterations", c_int32), ("launches", c_int32)]
+
+
+class GLMError(RuntimeError):
+    pass
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
+            "(or python -m paper_2510_14471_amd._build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    lib.glm_validate_shape.argtypes = [POINTER(GlmShape)]
+    lib.glm_validate_shape.restype = c_int
+    lib.glm_workspace_bytes.argtypes = [POINTER(GlmShape), c_int]
+    lib.glm_workspace_bytes.restype = c_size_t
+    lib.glm_qr_factor.argtypes = [POINTER(GlmShape), c_int, P, P, P, c_size_t, P,
+                                  POINTER(c_void_p)]
+    lib.glm_qr_factor.restype = c_int
+    lib.glm_gls_solve.argtypes = [P, P, P, P, c_double, c_int32, P, P, P, P, P, P]
+    lib.glm_gls_solve.restype = c_int
+    lib.glm_gls_backward.argtypes = [P, P, P, P, P, P, c_double, c_int32, P, P, P, P, P, P]
+    lib.glm_gls_backward.restype = c_int
+    lib.glm_copy_factors.argtypes = [P, P, P, P, P]
+    lib.glm_copy_factors.restype = c_int
+    lib.glm_get_stats.argtypes = [P, POINTER(GlmStats)]
+    lib.glm_get_stats.restype = c_int
+    lib.glm_profile_enable.argtypes = [P, c_int]
+    lib.glm_profile_enable.restype = c_int
+    lib.glm_profile_read.argtypes = [P, c_int, POINTER(c_int64), POINTER(c_double),
+                                     POINTER(c_double)]
+    lib.glm_profile_read.restype = c_int
+    lib.glm_factor_destroy.argtypes = [P]
+    lib.glm_factor_destroy.restype = None
+    lib.glm_strerror.argtypes = [c_int]
+    lib.glm_strerror.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = ["glm_validate_shape", "glm_workspace_bytes", "glm_qr_factor", "glm_gls_solve",
+            "glm_gls_backward", "glm_copy_factors", "glm_get_stats", "glm_profile_enable", "glm_profile_read",
+            "glm_factor_destroy", "glm_strerror"]
+
+
+def glm_strerror(code: int) -> str:
+    return _lib.glm_strerror(int(code)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != GLM_OK:
+        raise GLMError(f"{what}: {glm_strerror(rc)} ({rc})")
+
+
+class Shape:
+    """Host-side glm_shape: keeps the int32 arrays alive for the ctypes struct."""
+
+    def __init__(self, G, M, K, n_flat, k=None):
+        B = len(G)
+        self.B = B
+        self._G = (c_int32 * B)(*map(int, G))
+        self._M = (c_int32 * B)(*map(int, M))
+        self._K = (c_int32 * B)(*map(int, K))
+        self._k = (c_int32 * B)(*map(int, k)) if k is not None else None
+        self._n = (c_int32 * len(n_flat))(*map(int, n_flat))
+        self.struct = GlmShape(B, self._G, self._M, self._K, self._k, self._n)
+
+    def ptr(self):
+        return ctypes.byref(self.struct)
+
+
+def _dp(t):
+    """Device pointer of a tensor (or NULL for None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise GLMError("argument must be a device tensor")
+    if not t.is_contiguous():
+        raise GLMError("argument must be contiguous")
+    return c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def glm_validate_shape(shape: Shape) -> int:
+    return _lib.glm_validate_shape(shape.ptr())
+
+
+def glm_workspace_bytes(shape: Shape, precision: int) -> int:
+    return int(_lib.glm_workspace_bytes(shape.ptr(), int(precision)))
+
+
+def glm_qr_factor(shape: Shape, precision: int, X, Rc, ws, stream=None) -> c_void_p:
+    h = c_void_p()
+    rc = _lib.glm_qr_factor(shape.ptr(), int(precision), _dp(X), _dp(Rc), _dp(ws),
+                            ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(h))
+    _check(rc, "glm_qr_factor")
+    return h
+
+
+def glm_gls_solve(h, Omega, y, r, tol, max_iter, beta, u, uc, info, iters, stream=None) -> int:
+    rc = _lib.glm_gls_solve(h, _dp(Omega), _dp(y), _dp(r), float(tol), int(max_iter),
+                            _dp(beta), _dp(u), _dp(uc), _dp(info), _dp(iters), _stream(stream))
+    _check(rc, "glm_gls_solve")
+    return rc
+
+
+def glm_gls_backward(h, Omega, beta, u, g_beta, g_u, tol, max_iter, dy, dOmega, dX, info,
+                     iters, stream=None) -> int:
+    rc = _lib.glm_gls_backward(h, _dp(Omega), _dp(beta), _dp(u), _dp(g_beta), _dp(g_u),
+                               float(tol), int(max_iter), _dp(dy), _dp(dOmega), _dp(dX),
+                               _dp(info), _dp(iters), _stream(stream))
+    _check(rc, "glm_gls_backward")
+    return rc
+
+
+def glm_copy_factors(h, Q, R, rank, stream=None) -> int:
+    rc = _lib.glm_copy_factors(h, _dp(Q), _dp(R), _dp(rank), _stream(stream))
+    _check(rc, "glm_copy_factors")
+    return rc
+
+
+def glm_get_stats(h) -> dict:
+    st = GlmStats()
+    _check(_lib.glm_get_stats(h, ctypes.byref(st)), "glm_get_stats")
+    return {"outer_steps": st.outer_steps, "pcg_iterations": st.pcg_iterations,
+            "max_iterations": st.max_iterations, "launches": st.launches}
+
+
+def glm_profile_enable(h, on: bool):
+    _check(_lib.glm_profile_enable(h, int(bool(on))), "glm_profile_enable")
+
+
+def glm_profile_read(h, kernel_id: int):
+    n = c_int64()
+    ms = c_double()
+    by = c_double()
+    _check(_lib.glm_profile_read(h, int(kernel_id), ctypes.byref(n), ctypes.byref(ms),
+                                 ctypes.byref(by)), "glm_profile_read")
+    return int(n.value), float(ms.value), float(by.value)
+
+
+def glm_factor_destroy(h):
+    if h:
+        _lib.glm_factor_destroy(h)

@@ -1,0 +1,816 @@
+// Host orchestration and the C ABI (include/glm.h).
+//
+// glm_qr_factor builds the static plan (descriptors, tile schedule, workspace
+// layout), uploads it once and runs the batched QR.  glm_gls_solve runs the
+// PCG-Aug loop as a fixed sequence of launches per iteration
+//     pass A -> reduce T -> scalar A (lambda) -> pass B -> scalar B (mu, tests)
+// for all instances at once; converged (instance, rhs) pairs are masked on
+// the device and the host polls one counter every few iterations.  GLM_MIXED
+// wraps single-precision inner solves in double-precision iterative
+// refinement on the augmented system.
+#include "glm.h"
+#include "glm_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace glm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kLdsBudget = 48 * 1024;  // dynamic LDS per workgroup (U and B slabs)
+constexpr int kTargetTiles = 2048;        // row tiles over the whole batch
+constexpr int kMinTileRows = 64;          // keeps the per-tile partial sums small
+constexpr int kPollEvery = 8;             // iterations between host convergence polls
+constexpr int kStallFP64 = 200;           // iterations in which c must halve at least once
+constexpr int kStallInner = 40;
+constexpr double kInnerTol = 1e-5;        // inner single-precision relative tolerance
+constexpr int kInnerMaxit = 20000;        // cap of one inner solve
+constexpr int kMaxOuter = 12;             // refinement steps
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Progress trace on stderr when the environment variable GLM_LOG is set.
+bool log_on() {
+  static const bool on = std::getenv("GLM_LOG") != nullptr;
+  return on;
+}
+
+double now_s() {
+  using clk = std::chrono::steady_clock;
+  static const clk::time_point t0 = clk::now();
+  return std::chrono::duration<double>(clk::now() - t0).count();
+}
+
+struct Plan {
+  int B = 0;
+  glm_precision prec = GLM_FP64;
+  std::vector<InstDesc> inst;
+  std::vector<BlockDesc> blk;
+  std::vector<TileDesc> tile;
+  std::vector<QRJob> qr_sur, qr_nb;
+  std::vector<RedChunk> chunks;
+  std::vector<int> rinst, rinst_index, colblk;
+  int64_t sumMn = 0, sumMGK = 0, sumnK = 0, sumTK = 0, sumG2 = 0, sumR = 0, sumNb = 0,
+          sumCK = 0, sumTp = 0, sumRc = 0;
+  int nrhs = 0, ntiles = 0, nblk = 0, maxK = 0, maxn = 0, maxni = 0, maxkc = 0;
+  int kc_t = 1, sl = 1;
+  size_t lds_inner = 0, lds64 = 0;
+  // byte offsets inside the workspace
+  size_t o_Q64, o_Q32, o_R, o_Nb, o_colblk, o_inst, o_blk, o_tile, o_qrs, o_qrn, o_chunks,
+      o_rinst, o_rinst_index, o_flags, o_active, o_icount, o_count, o_st, o_ost, o_alpha,
+      o_Om32, o_g, o_u, o_wf, o_yf, o_Tpart, o_Tm, o_dpart, o_cpart, o_gc, o_uc, o_wc,
+      o_wc64, o_rho0, o_rhoc, o_lb, o_bytes;
+  size_t total = 0;
+};
+
+int pick_kc(int k) {
+  int v = 1;
+  while (v < k) v <<= 1;
+  return v;
+}
+
+int validate(const glm_shape* s) {
+  if (!s || s->batch < 1 || !s->G || !s->M || !s->K || !s->n) return GLM_EINVAL;
+  int64_t off = 0;
+  for (int b = 0; b < s->batch; ++b) {
+    const int G = s->G[b], M = s->M[b], K = s->K[b], kc = s->k ? s->k[b] : 0;
+    if (G < 1 || M < 1 || K < 1 || K > KMAX || kc < 0) return GLM_EINVAL;
+    int64_t n = 0;
+    for (int i = 0; i < G; ++i) {
+      const int ni = s->n[off + i];
+      if (ni < 1 || ni > M) return GLM_EINVAL;
+      if (ni > QR_NMAX) return GLM_EUNSUPPORTED;
+      n += ni;
+    }
+    off += G;
+    if (kc > n) return GLM_EINVAL;
+    if (n >= (int64_t)G * M + kc) return GLM_EINVAL;  // m + k > n needed for the augmented system
+    if (kc > 64) return GLM_EUNSUPPORTED;
+    // column slots per thread of the projection passes: up to 4 for any K,
+    // up to 8 (n <= 2048) when K <= 4
+    if (n > 8 * NT) return GLM_EUNSUPPORTED;
+    const int slots = (int)((n + NT - 1) / NT);
+    if (slots > 4 && pick_kc(K) > 4) return GLM_EUNSUPPORTED;
+    if ((int64_t)G * G > 64 * 1024) return GLM_EUNSUPPORTED;
+  }
+  return GLM_OK;
+}
+
+int make_plan(const glm_shape* s, glm_precision prec, Plan& p) {
+  int rc = validate(s);
+  if (rc != GLM_OK) return rc;
+  p = Plan();
+  p.B = s->batch;
+  p.prec = prec;
+  const size_t sv = (prec == GLM_MIXED) ? sizeof(float) : sizeof(double);
+  int64_t sum_rows = 0;
+  for (int b = 0; b < p.B; ++b) sum_rows += s->M[b];
+  int rc_rows = (int)std::max<int64_t>(kMinTileRows, (sum_rows + kTargetTiles - 1) / kTargetTiles);
+  int64_t noff = 0;
+  for (int b = 0; b < p.B; ++b) {
+    InstDesc in{};
+    in.G = s->G[b];
+    in.M = s->M[b];
+    in.K = s->K[b];
+    in.kc = s->k ? s->k[b] : 0;
+    int n = 0;
+    for (int i = 0; i < in.G; ++i) n += s->n[noff + i];
+    in.n = n;
+    in.blk0 = (int)p.blk.size();
+    in.rhs0 = p.nrhs;
+    in.q_off = p.sumMn;
+    in.v_off = p.sumMGK;
+    in.om_off = p.sumG2;
+    in.b_off = p.sumnK;
+    in.t_off = p.sumTK;
+    in.col_off = (int64_t)p.colblk.size();
+    in.c_off = p.sumCK;
+    in.rc_off = p.sumRc;
+    in.nb_off = p.sumNb;
+    in.maxit = (int)std::min<int64_t>((int64_t)in.G * in.M + in.kc - n + 1, 1 << 30);
+    const size_t per_row = 2 * (size_t)in.G * in.K;
+    in.rs = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * sv)));
+    in.rs64 = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * 8)));
+    p.lds_inner = std::max(p.lds_inner, per_row * sv * in.rs);
+    p.lds64 = std::max(p.lds64, per_row * 8 * in.rs64);
+    // blocks
+    int col = 0;
+    for (int i = 0; i < in.G; ++i) {
+      const int ni = s->n[noff + i];
+      BlockDesc bd{};
+      bd.inst = b;
+      bd.eq = i;
+      bd.col = col;
+      bd.ni = ni;
+      bd.r_off = p.sumR;
+      p.sumR += (int64_t)ni * ni;
+      QRJob qj{};
+      qj.a_off = in.q_off + col;
+      qj.rows = in.M;
+      qj.cols = ni;
+      qj.ld = n;
+      qj.flag = (int)p.blk.size();
+      qj.r_off = bd.r_off;
+      p.qr_sur.push_back(qj);
+      p.blk.push_back(bd);
+      for (int c = 0; c < ni; ++c) p.colblk.push_back(i);
+      col += ni;
+      p.maxni = std::max(p.maxni, ni);
+    }
+    noff += in.G;
+    // tiles: rows per tile a multiple of both sub-tile heights
+    int step = std::max(in.rs, in.rs64);
+    int trows = std::max(step, (rc_rows + step - 1) / step * step);
+    in.tile0 = (int)p.tile.size();
+    in.tp_stride = std::max<int64_t>((int64_t)n * in.K, (int64_t)in.G * in.G);
+    int part = 0;
+    for (int r0 = 0; r0 < in.M; r0 += trows) {
+      TileDesc td{};
+      td.inst = b;
+      td.row0 = r0;
+      td.rows = std::min(trows, in.M - r0);
+      td.part = part++;
+      td.tp_off = p.sumTp;
+      p.sumTp += in.tp_stride;
+      p.tile.push_back(td);
+    }
+    in.ntiles = part;
+    for (int p0 = 0; p0 < n * in.K; p0 += NT) p.chunks.push_back(RedChunk{b, p0});
+    if (in.kc > 0) {
+      p.rinst_index.push_back((int)p.rinst.size());
+      QRJob qj{};
+      qj.a_off = in.nb_off;
+      qj.rows = n + in.kc;
+      qj.cols = in.kc;
+      qj.ld = in.kc;
+      qj.flag = -1;  // set below
+      qj.r_off = -1;
+      p.qr_nb.push_back(qj);
+      p.rinst.push_back(b);
+      p.maxkc = std::max(p.maxkc, in.kc);
+    } else {
+      p.rinst_index.push_back(-1);
+    }
+    p.sumMn += (int64_t)in.M * n;
+    p.sumMGK += (int64_t)in.M * in.G * in.K;
+    p.sumnK += (int64_t)n * in.K;
+    p.sumTK += (int64_t)(n + in.kc) * in.K;
+    p.sumG2 += (int64_t)in.G * in.G;
+    p.sumCK += (int64_t)in.kc * in.K;
+    p.sumRc += (int64_t)in.kc * n;
+    p.sumNb += (int64_t)(n + in.kc) * in.kc;
+    p.nrhs += in.K;
+    p.maxK = std::max(p.maxK, in.K);
+    p.maxn = std::max(p.maxn, n);
+    p.inst.push_back(in);
+  }
+  p.nblk = (int)p.blk.size();
+  p.ntiles = (int)p.tile.size();
+  for (size_t r = 0; r < p.qr_nb.size(); ++r) p.qr_nb[r].flag = p.nblk + (int)r;
+  p.kc_t = pick_kc(p.maxK);
+  const int slots = (p.maxn + NT - 1) / NT;
+  p.sl = slots <= 4 ? slots : 8;
+  if (p.kc_t > 4 && p.sl == 8) return GLM_EUNSUPPORTED;  // mixed K / n extremes in one batch
+  // layout
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  p.o_Q64 = take(8 * p.sumMn);
+  p.o_Q32 = take(prec == GLM_MIXED ? 4 * p.sumMn : 0);
+  p.o_R = take(8 * p.sumR);
+  p.o_Nb = take(8 * p.sumNb);
+  p.o_colblk = take(4 * p.colblk.size());
+  p.o_inst = take(sizeof(InstDesc) * p.inst.size());
+  p.o_blk = take(sizeof(BlockDesc) * p.blk.size());
+  p.o_tile = take(sizeof(TileDesc) * p.tile.size());
+  p.o_qrs = take(sizeof(QRJob) * p.qr_sur.size());
+  p.o_qrn = take(sizeof(QRJob) * p.qr_nb.size());
+  p.o_chunks = take(sizeof(RedChunk) * p.chunks.size());
+  p.o_rinst = take(4 * p.rinst.size());
+  p.o_rinst_index = take(4 * p.rinst_index.size());
+  p.o_flags = take(4 * (p.nblk + p.rinst.size()));
+  p.o_active = take(4 * p.B);
+  p.o_icount = take(4 * p.B);
+  p.o_count = take(16);
+  p.o_st = take(sizeof(RhsState) * p.nrhs);
+  p.o_ost = take(4 * p.nrhs);
+  p.o_alpha = take(8 * p.B);
+  p.o_Om32 = take(prec == GLM_MIXED ? 4 * p.sumG2 : 0);
+  p.o_g = take(sv * p.sumMGK);
+  p.o_u = take(sv * p.sumMGK);
+  p.o_wf = take(prec == GLM_MIXED ? 4 * p.sumMGK : 0);
+  p.o_yf = take(prec == GLM_MIXED ? 4 * p.sumMGK : 0);
+  p.o_Tpart = take(8 * p.sumTp);
+  p.o_Tm = take(8 * p.sumTK);
+  p.o_dpart = take(8 * (size_t)p.ntiles * KMAX);
+  p.o_cpart = take(8 * (size_t)p.ntiles * KMAX);
+  p.o_gc = take(8 * p.sumCK);
+  p.o_uc = take(8 * p.sumCK);
+  p.o_wc = take(8 * p.sumCK);
+  p.o_wc64 = take(8 * p.sumCK);
+  p.o_rho0 = take(8 * p.sumnK);
+  p.o_rhoc = take(8 * p.sumCK);
+  p.o_lb = take(8 * p.sumnK);
+  p.o_bytes = take(2 * sizeof(unsigned long long));
+  p.total = o;
+  return GLM_OK;
+}
+
+struct EventPair {
+  hipEvent_t a, b;
+  int kid;
+};
+
+}  // namespace
+
+struct glm_factor {
+  Plan p;
+  char* ws = nullptr;
+  const double* X = nullptr;
+  const double* Rc = nullptr;
+  int* h_count = nullptr;   // pinned
+  glm_stats stats{};
+  bool prof = false;
+  std::vector<EventPair> ev_used, ev_free;
+  int64_t prof_launch[2] = {0, 0};
+  double prof_ms[2] = {0, 0};
+  int launches = 0;
+
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+  const InstDesc* d_inst() const { return at<InstDesc>(p.o_inst); }
+  const TileDesc* d_tile() const { return at<TileDesc>(p.o_tile); }
+  const BlockDesc* d_blk() const { return at<BlockDesc>(p.o_blk); }
+  int* d_active() const { return at<int>(p.o_active); }
+  RhsState* d_st() const { return at<RhsState>(p.o_st); }
+};
+
+namespace {
+
+#define GLM_CHECK(expr)                        \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return GLM_EHIP;     \
+  } while (0)
+
+EventPair get_event(glm_factor* f, int kid) {
+  EventPair e;
+  if (!f->ev_free.empty()) {
+    e = f->ev_free.back();
+    f->ev_free.pop_back();
+  } else {
+    (void)hipEventCreate(&e.a);
+    (void)hipEventCreate(&e.b);
+  }
+  e.kid = kid;
+  return e;
+}
+
+template <typename T>
+PassLaunch<T> pass_args(glm_factor* f, const T* Q, const T* Om, const T* y, T* w, T* g, T* u,
+                        bool prof) {
+  const Plan& p = f->p;
+  PassLaunch<T> a{};
+  a.insts = f->d_inst();
+  a.tiles = f->d_tile();
+  a.ntiles = p.ntiles;
+  a.blks = f->d_blk();
+  a.colblk = f->at<int>(p.o_colblk);
+  a.inst_active = f->d_active();
+  a.Q = Q;
+  a.Om = Om;
+  a.alpha = f->at<double>(p.o_alpha);
+  a.st = f->d_st();
+  a.y = y;
+  a.w = w;
+  a.g = g;
+  a.u = u;
+  a.Tm = f->at<T>(p.o_Tm);
+  a.Tpart = f->at<T>(p.o_Tpart);
+  a.dpart = f->at<double>(p.o_dpart);
+  a.cpart = f->at<double>(p.o_cpart);
+  a.bytes = prof ? f->at<unsigned long long>(p.o_bytes) : nullptr;
+  a.w_nonzero = 0;
+  a.kc_t = p.kc_t;
+  a.sl = p.sl;
+  a.lds = (sizeof(T) == 8) ? p.lds64 : p.lds_inner;
+  return a;
+}
+
+template <typename T>
+int run_pass_a(glm_factor* f, PassLaunch<T> a, int mode, hipStream_t s) {
+  const bool timed = f->prof && mode == PASS_A_ITER;
+  EventPair e{};
+  if (timed) {
+    e = get_event(f, 0);
+    GLM_CHECK(hipEventRecord(e.a, s));
+    a.bytes = f->at<unsigned long long>(f->p.o_bytes);
+  } else {
+    a.bytes = nullptr;
+  }
+  GLM_CHECK(launch_pass_a<T>(a, mode, s));
+  ++f->launches;
+  if (timed) {
+    GLM_CHECK(hipEventRecord(e.b, s));
+    f->ev_used.push_back(e);
+  }
+  return GLM_OK;
+}
+
+template <typename T>
+int run_pass_b(glm_factor* f, PassLaunch<T> a, int mode, hipStream_t s) {
+  const bool timed = f->prof && mode == PASS_B_ITER;
+  EventPair e{};
+  if (timed) {
+    e = get_event(f, 1);
+    GLM_CHECK(hipEventRecord(e.a, s));
+    a.bytes = f->at<unsigned long long>(f->p.o_bytes) + 1;
+  } else {
+    a.bytes = nullptr;
+  }
+  GLM_CHECK(launch_pass_b<T>(a, mode, s));
+  ++f->launches;
+  if (timed) {
+    GLM_CHECK(hipEventRecord(e.b, s));
+    f->ev_used.push_back(e);
+  }
+  return GLM_OK;
+}
+
+// Projection  T <- [Q^T (y - Sigma w) ; r]  followed by the restriction correction.
+template <typename T>
+int project_rhs(glm_factor* f, const T* Q, const T* Om, const T* y, T* w, bool w_nonzero,
+                const double* rvec, hipStream_t s) {
+  const Plan& p = f->p;
+  PassLaunch<T> a = pass_args<T>(f, Q, Om, y, w, nullptr, nullptr, false);
+  a.w_nonzero = w_nonzero;
+  if (int rc = run_pass_a<T>(f, a, PASS_A_RHS, s)) return rc;
+  GLM_CHECK(launch_reduce_t<T>(f->d_inst(), f->d_tile(), f->d_active(),
+                               f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
+                               f->at<T>(p.o_Tpart), f->at<T>(p.o_Tm), s));
+  GLM_CHECK(launch_scalar_a<T>(f->d_inst(), f->d_tile(), f->d_active(), f->d_st(),
+                               f->at<double>(p.o_dpart), f->at<T>(p.o_Tm),
+                               f->at<double>(p.o_Nb), rvec, p.B, 0, 0, s));
+  f->launches += 3;
+  return GLM_OK;
+}
+
+// One PCG-Aug solve of [Sigma X; X^T 0][w; beta] = [y; h2] (+ restriction rows r)
+// in precision T for every (instance, rhs) whose state is ST_ACTIVE.
+// beta_out receives (or, with beta_add, accumulates) the estimate.
+template <typename T>
+int core_solve(glm_factor* f, const T* Q, const T* Om, const T* y, const double* h2,
+               const double* rvec, T* w, double* beta_out, bool beta_add, double tol,
+               int stall, int maxit_cap, hipStream_t s) {
+  const Plan& p = f->p;
+  T* g = f->at<T>(p.o_g);
+  T* u = f->at<T>(p.o_u);
+  T* Tm = f->at<T>(p.o_Tm);
+  double* gc = f->at<double>(p.o_gc);
+  double* uc = f->at<double>(p.o_uc);
+  double* wc = f->at<double>(p.o_wc);
+  const bool t_double = sizeof(T) == 8;
+  // start: w_1 = X* h2 (zero without a lower right-hand side)
+  GLM_CHECK(launch_fill<T>(w, p.sumMGK, T(0), s));
+  GLM_CHECK(launch_fill<double>(wc, std::max<int64_t>(p.sumCK, 0), 0.0, s));
+  f->launches += 2;
+  bool w_nonzero = false;
+  if (h2) {
+    GLM_CHECK((launch_trisolve<double, T, false, false>(f->d_inst(), f->d_blk(), p.nblk,
+                                                        f->d_active(), f->d_st(), 1,
+                                                        f->at<double>(p.o_R), h2, 0, Tm, 1, s)));
+    GLM_CHECK(launch_scalar_a<T>(f->d_inst(), f->d_tile(), f->d_active(), f->d_st(),
+                                 f->at<double>(p.o_dpart), Tm, f->at<double>(p.o_Nb), nullptr,
+                                 p.B, 1, 0, s));
+    PassLaunch<T> a = pass_args<T>(f, Q, Om, y, w, g, u, false);
+    if (int rc = run_pass_b<T>(f, a, PASS_B_EXPAND, s)) return rc;
+    if (p.sumCK) GLM_CHECK(launch_copy_tc<T>(f->d_inst(), p.B, Tm, wc, s));
+    f->launches += 3;
+    w_nonzero = true;
+  }
+  // g_1 = -Pi (y - Sigma w_1), c_1
+  if (int rc = project_rhs<T>(f, Q, Om, y, w, w_nonzero, rvec, s)) return rc;
+  {
+    PassLaunch<T> a = pass_args<T>(f, Q, Om, y, w, g, u, false);
+    a.w_nonzero = w_nonzero;
+    if (int rc = run_pass_b<T>(f, a, PASS_B_INIT, s)) return rc;
+  }
+  GLM_CHECK(launch_scalar_b(f->d_inst(), f->d_active(), f->at<int>(p.o_icount), f->d_st(),
+                            f->at<double>(p.o_cpart), f->at<double>(p.o_alpha), Tm, t_double,
+                            gc, uc, wc, rvec, p.B, 0, tol, stall, maxit_cap, s));
+  ++f->launches;
+  // iterations
+  int64_t maxit_all = 0;
+  for (const auto& in : p.inst) maxit_all = std::max<int64_t>(maxit_all, in.maxit);
+  if (maxit_cap > 0) maxit_all = std::min<int64_t>(maxit_all, maxit_cap);
+  PassLaunch<T> aa = pass_args<T>(f, Q, Om, y, w, g, u, false);
+  for (int64_t it = 0; it < maxit_all + 1; ++it) {
+    if (it % kPollEvery == 0) {
+      GLM_CHECK(launch_count(f->at<int>(p.o_icount), p.B, f->at<int>(p.o_count), s));
+      GLM_CHECK(hipMemcpyAsync(f->h_count, f->at<int>(p.o_count), sizeof(int),
+                               hipMemcpyDeviceToHost, s));
+      GLM_CHECK(hipStreamSynchronize(s));
+      if (log_on() && (it % (kPollEvery * 16) == 0 || *f->h_count == 0))
+        std::fprintf(stderr, "[glm %.3fs] %s pcg it %lld active rhs %d\n", now_s(),
+                     sizeof(T) == 8 ? "fp64" : "fp32", (long long)it, *f->h_count);
+      if (*f->h_count == 0) break;
+    }
+    if (int rc = run_pass_a<T>(f, aa, PASS_A_ITER, s)) return rc;
+    GLM_CHECK(launch_reduce_t<T>(f->d_inst(), f->d_tile(), f->d_active(),
+                                 f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
+                                 f->at<T>(p.o_Tpart), Tm, s));
+    GLM_CHECK(launch_scalar_a<T>(f->d_inst(), f->d_tile(), f->d_active(), f->d_st(),
+                                 f->at<double>(p.o_dpart), Tm, f->at<double>(p.o_Nb),
+                                 nullptr, p.B, 1, 1, s));
+    if (int rc = run_pass_b<T>(f, aa, PASS_B_ITER, s)) return rc;
+    GLM_CHECK(launch_scalar_b(f->d_inst(), f->d_active(), f->at<int>(p.o_icount), f->d_st(),
+                              f->at<double>(p.o_cpart), f->at<double>(p.o_alpha), Tm,
+                              t_double, gc, uc, wc, nullptr, p.B, 1, tol, stall, maxit_cap,
+                              s));
+    f->launches += 3;
+  }
+  // termination: beta = X*^T (y - Sigma w) for every solved rhs
+  GLM_CHECK(launch_activate(f->d_inst(), p.B, f->d_st(), f->d_active(), s));
+  if (int rc = project_rhs<T>(f, Q, Om, y, w, true, rvec, s)) return rc;
+  if (beta_add) {
+    GLM_CHECK((launch_trisolve<T, double, true, true>(f->d_inst(), f->d_blk(), p.nblk,
+                                                      f->d_active(), f->d_st(), 1,
+                                                      f->at<double>(p.o_R), Tm, 1, beta_out,
+                                                      0, s)));
+  } else {
+    GLM_CHECK((launch_trisolve<T, double, true, false>(f->d_inst(), f->d_blk(), p.nblk,
+                                                       f->d_active(), f->d_st(), 1,
+                                                       f->at<double>(p.o_R), Tm, 1, beta_out,
+                                                       0, s)));
+  }
+  f->launches += 2;
+  return GLM_OK;
+}
+
+int map_info_and_stats(glm_factor* f, int32_t* info, int32_t* iters, bool mixed,
+                       hipStream_t s) {
+  const Plan& p = f->p;
+  std::vector<RhsState> st(p.nrhs);
+  std::vector<int> ost(p.nrhs, 0);
+  GLM_CHECK(hipMemcpyAsync(st.data(), f->d_st(), sizeof(RhsState) * p.nrhs,
+                           hipMemcpyDeviceToHost, s));
+  if (mixed)
+    GLM_CHECK(hipMemcpyAsync(ost.data(), f->at<int>(p.o_ost), 4 * p.nrhs,
+                             hipMemcpyDeviceToHost, s));
+  GLM_CHECK(hipStreamSynchronize(s));
+  std::vector<int32_t> hinfo(p.nrhs), hit(p.nrhs);
+  int64_t tot = 0;
+  int mx = 0;
+  for (int r = 0; r < p.nrhs; ++r) {
+    const int stt = mixed ? ost[r] : st[r].status;
+    int code;
+    switch (stt) {
+      case ST_CONVERGED: code = GLM_INFO_CONVERGED; break;
+      case ST_STAGNATED: code = GLM_INFO_STAGNATED; break;
+      case ST_BREAKDOWN: code = GLM_INFO_BREAKDOWN; break;
+      case ST_RANK: code = GLM_INFO_RANK; break;
+      default: code = GLM_INFO_NOCONV; break;
+    }
+    hinfo[r] = code;
+    hit[r] = st[r].total_iters;
+    tot += st[r].total_iters;
+    mx = std::max(mx, st[r].total_iters);
+  }
+  f->stats.pcg_iterations = tot;
+  f->stats.max_iterations = mx;
+  if (info)
+    GLM_CHECK(hipMemcpyAsync(info, hinfo.data(), 4 * p.nrhs, hipMemcpyHostToDevice, s));
+  if (iters)
+    GLM_CHECK(hipMemcpyAsync(iters, hit.data(), 4 * p.nrhs, hipMemcpyHostToDevice, s));
+  GLM_CHECK(hipStreamSynchronize(s));
+  return GLM_OK;
+}
+
+// Common driver of solve and backward: y (may be null = 0), h2 (may be null),
+// rvec (may be null) -> beta_out, u_out (double), uc_out (may be null).
+int solve_driver(glm_factor* f, const double* Om, const double* y, const double* h2,
+                 const double* rvec, double tol, int32_t max_iter, double* beta_out,
+                 double* u_out, double* uc_out, int32_t* info, int32_t* iters, hipStream_t s) {
+  const Plan& p = f->p;
+  f->launches = 0;
+  f->stats = glm_stats{};
+  const bool mixed = p.prec == GLM_MIXED;
+  GLM_CHECK(launch_alpha(f->d_inst(), p.B, Om, f->at<double>(p.o_alpha),
+                         mixed ? f->at<float>(p.o_Om32) : nullptr, s));
+  GLM_CHECK(launch_state_init(f->d_inst(), p.B, f->at<int>(p.o_flags), p.nblk,
+                              f->at<int>(p.o_rinst_index), f->d_st(), f->d_active(),
+                              f->at<int>(p.o_ost), s));
+  GLM_CHECK(launch_fill<double>(beta_out, p.sumnK, 0.0, s));
+  f->launches += 3;
+  if (!mixed) {
+    int rc = core_solve<double>(f, f->at<double>(p.o_Q64), Om, y, h2, rvec, u_out, beta_out,
+                                false, tol, kStallFP64, max_iter, s);
+    if (rc) return rc;
+    f->stats.outer_steps = 1;
+    if (uc_out && p.sumCK)
+      GLM_CHECK(hipMemcpyAsync(uc_out, f->at<double>(p.o_wc), 8 * p.sumCK,
+                               hipMemcpyDeviceToDevice, s));
+  } else {
+    double* wc64 = f->at<double>(p.o_wc64);
+    GLM_CHECK(launch_fill<double>(u_out, p.sumMGK, 0.0, s));
+    GLM_CHECK(launch_fill<double>(wc64, std::max<int64_t>(p.sumCK, 0), 0.0, s));
+    f->launches += 2;
+    float* yf = f->at<float>(p.o_yf);
+    float* wf = f->at<float>(p.o_wf);
+    int step = 0;
+    for (step = 0; step <= kMaxOuter; ++step) {
+      // double-precision residual of the augmented system
+      GLM_CHECK(launch_residual(f->d_inst(), f->d_tile(), p.ntiles, f->d_blk(),
+                                f->at<int>(p.o_colblk), f->d_active(), f->X, Om, y, u_out,
+                                beta_out, yf, f->at<double>(p.o_Tpart),
+                                f->at<double>(p.o_cpart), f->at<double>(p.o_dpart), p.kc_t,
+                                p.sl, p.lds64, s));
+      GLM_CHECK(launch_reduce_t<double>(f->d_inst(), f->d_tile(), f->d_active(),
+                                        f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
+                                        f->at<double>(p.o_Tpart), f->at<double>(p.o_Tm), s));
+      GLM_CHECK(launch_outer_check(f->d_inst(), p.B, f->d_active(), f->d_st(),
+                                   f->at<int>(p.o_ost), f->at<double>(p.o_cpart),
+                                   f->at<double>(p.o_dpart), f->at<double>(p.o_Tm), h2, f->Rc,
+                                   rvec, beta_out, wc64, f->at<double>(p.o_rho0),
+                                   f->at<double>(p.o_rhoc), tol, step, step == kMaxOuter, s));
+      f->launches += 3;
+      // anything left?
+      GLM_CHECK(launch_count(f->d_active(), p.B, f->at<int>(p.o_count), s));
+      GLM_CHECK(hipMemcpyAsync(f->h_count, f->at<int>(p.o_count), sizeof(int),
+                               hipMemcpyDeviceToHost, s));
+      GLM_CHECK(hipStreamSynchronize(s));
+      if (log_on())
+        std::fprintf(stderr, "[glm %.3fs] refinement step %d: %d instances need work\n",
+                     now_s(), step, *f->h_count);
+      if (*f->h_count == 0) break;
+      int rc = core_solve<float>(f, f->at<float>(p.o_Q32), f->at<float>(p.o_Om32), yf,
+                                 f->at<double>(p.o_rho0),
+                                 p.sumCK ? f->at<double>(p.o_rhoc) : nullptr, wf, beta_out,
+                                 true, kInnerTol, kStallInner,
+                                 (max_iter > 0 && max_iter < kInnerMaxit) ? max_iter
+                                                                          : kInnerMaxit,
+                                 s);
+      if (rc) return rc;
+      GLM_CHECK(launch_update_u(f->d_inst(), f->d_tile(), p.ntiles, f->d_active(), f->d_st(),
+                                wf, u_out, s));
+      if (p.sumCK)
+        GLM_CHECK(launch_update_c(f->d_inst(), p.B, f->d_st(), f->at<double>(p.o_wc), wc64, s));
+      f->launches += 2;
+    }
+    f->stats.outer_steps = step;
+    if (uc_out && p.sumCK)
+      GLM_CHECK(hipMemcpyAsync(uc_out, wc64, 8 * p.sumCK, hipMemcpyDeviceToDevice, s));
+  }
+  f->stats.launches = f->launches;
+  return map_info_and_stats(f, info, iters, mixed, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int glm_validate_shape(const glm_shape* shape) { return validate(shape); }
+
+size_t glm_workspace_bytes(const glm_shape* shape, glm_precision prec) {
+  if (prec != GLM_FP64 && prec != GLM_MIXED) return 0;
+  Plan p;
+  if (make_plan(shape, prec, p) != GLM_OK) return 0;
+  return p.total;
+}
+
+int glm_qr_factor(const glm_shape* shape, glm_precision prec, const double* X,
+                  const double* Rc, void* ws, size_t ws_bytes, hipStream_t stream,
+                  glm_factor** out) {
+  if (!out || !X) return GLM_EINVAL;
+  *out = nullptr;
+  if (prec != GLM_FP64 && prec != GLM_MIXED) return GLM_EINVAL;
+  glm_factor* f = new (std::nothrow) glm_factor();
+  if (!f) return GLM_EINVAL;
+  int rc = make_plan(shape, prec, f->p);
+  if (rc != GLM_OK) {
+    delete f;
+    return rc;
+  }
+  const Plan& p = f->p;
+  if (p.sumRc > 0 && !Rc) {
+    delete f;
+    return GLM_EINVAL;
+  }
+  if (!ws || ws_bytes < p.total) {
+    delete f;
+    return GLM_EWORKSPACE;
+  }
+  f->ws = static_cast<char*>(ws);
+  f->X = X;
+  f->Rc = Rc;
+  if (hipHostMalloc((void**)&f->h_count, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+    delete f;
+    return GLM_EHIP;
+  }
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(f->ws + off, src, bytes, hipMemcpyHostToDevice, stream);
+  };
+  hipError_t e = hipSuccess;
+  if (!e) e = up(p.o_inst, p.inst.data(), sizeof(InstDesc) * p.inst.size());
+  if (!e) e = up(p.o_blk, p.blk.data(), sizeof(BlockDesc) * p.blk.size());
+  if (!e) e = up(p.o_tile, p.tile.data(), sizeof(TileDesc) * p.tile.size());
+  if (!e) e = up(p.o_qrs, p.qr_sur.data(), sizeof(QRJob) * p.qr_sur.size());
+  if (!e) e = up(p.o_qrn, p.qr_nb.data(), sizeof(QRJob) * p.qr_nb.size());
+  if (!e) e = up(p.o_chunks, p.chunks.data(), sizeof(RedChunk) * p.chunks.size());
+  if (!e) e = up(p.o_rinst, p.rinst.data(), 4 * p.rinst.size());
+  if (!e) e = up(p.o_rinst_index, p.rinst_index.data(), 4 * p.rinst_index.size());
+  if (!e) e = up(p.o_colblk, p.colblk.data(), 4 * p.colblk.size());
+  // the host descriptor vectors must outlive the asynchronous copies
+  if (!e) e = hipStreamSynchronize(stream);
+  if (!e) e = hipMemcpyAsync(f->ws + p.o_Q64, X, 8 * p.sumMn, hipMemcpyDeviceToDevice, stream);
+  if (!e) e = launch_fill<int>(f->at<int>(p.o_flags), p.nblk + (int64_t)p.rinst.size(), 0, stream);
+  if (!e)
+    e = launch_qr(f->at<QRJob>(p.o_qrs), (int)p.qr_sur.size(), p.maxni, f->at<double>(p.o_Q64),
+                  f->at<double>(p.o_R), f->at<int>(p.o_flags), stream);
+  if (!e && !p.rinst.empty()) {
+    e = launch_nullbasis_input(f->d_inst(), f->at<int>(p.o_rinst), (int)p.rinst.size(),
+                               f->d_blk(), f->at<double>(p.o_R), Rc, f->at<double>(p.o_Nb),
+                               stream);
+    if (!e)
+      e = launch_qr(f->at<QRJob>(p.o_qrn), (int)p.qr_nb.size(), p.maxkc,
+                    f->at<double>(p.o_Nb), f->at<double>(p.o_R), f->at<int>(p.o_flags), stream);
+  }
+  if (!e && prec == GLM_MIXED)
+    e = launch_to_float(f->at<double>(p.o_Q64), f->at<float>(p.o_Q32), p.sumMn, stream);
+  if (e != hipSuccess) {
+    (void)hipHostFree(f->h_count);
+    delete f;
+    return GLM_EHIP;
+  }
+  *out = f;
+  return GLM_OK;
+}
+
+int glm_gls_solve(glm_factor* f, const double* Omega, const double* y, const double* r,
+                  double tol, int32_t max_iter, double* beta, double* u, double* uc,
+                  int32_t* info, int32_t* iters, hipStream_t stream) {
+  if (!f || !Omega || !y || !beta || !u) return GLM_EINVAL;
+  if (f->p.sumCK > 0 && !r) return GLM_EINVAL;
+  if (!(tol >= 0.0)) return GLM_EINVAL;
+  return solve_driver(f, Omega, y, nullptr, r, tol, max_iter, beta, u, uc, info, iters, stream);
+}
+
+int glm_gls_backward(glm_factor* f, const double* Omega, const double* beta, const double* u,
+                     const double* g_beta, const double* g_u, double tol, int32_t max_iter,
+                     double* dy, double* dOmega, double* dX, int32_t* info, int32_t* iters,
+                     hipStream_t stream) {
+  if (!f || !Omega || !beta || !u || !g_beta || !dy) return GLM_EINVAL;
+  if (!(tol >= 0.0)) return GLM_EINVAL;
+  const Plan& p = f->p;
+  double* lb = f->at<double>(p.o_lb);
+  // adjoint system [Sigma X; X^T 0][l_u; l_beta] = [g_u; g_beta] (restriction rows: 0)
+  int rc = solve_driver(f, Omega, g_u, g_beta, nullptr, tol, max_iter, lb, dy, nullptr, info,
+                        iters, stream);
+  if (rc) return rc;
+  GLM_CHECK(launch_grad(f->d_inst(), f->d_tile(), p.ntiles, p.B, f->at<int>(p.o_colblk), dy, u,
+                        beta, lb, f->at<double>(p.o_Tpart), dOmega, dX, stream));
+  GLM_CHECK(hipStreamSynchronize(stream));
+  return GLM_OK;
+}
+
+int glm_copy_factors(const glm_factor* f, double* Q, double* R, int32_t* rank,
+                     hipStream_t stream) {
+  if (!f) return GLM_EINVAL;
+  const Plan& p = f->p;
+  if (Q)
+    GLM_CHECK(hipMemcpyAsync(Q, f->ws + p.o_Q64, 8 * p.sumMn, hipMemcpyDeviceToDevice, stream));
+  if (R)
+    GLM_CHECK(hipMemcpyAsync(R, f->ws + p.o_R, 8 * p.sumR, hipMemcpyDeviceToDevice, stream));
+  if (rank)
+    GLM_CHECK(hipMemcpyAsync(rank, f->ws + p.o_flags, 4 * (size_t)p.nblk,
+                             hipMemcpyDeviceToDevice, stream));
+  return GLM_OK;
+}
+
+int glm_get_stats(const glm_factor* f, glm_stats* out) {
+  if (!f || !out) return GLM_EINVAL;
+  *out = f->stats;
+  return GLM_OK;
+}
+
+int glm_profile_enable(glm_factor* f, int on) {
+  if (!f) return GLM_EINVAL;
+  f->prof = on != 0;
+  return GLM_OK;
+}
+
+int glm_profile_read(glm_factor* f, int kernel_id, int64_t* launches, double* total_ms,
+                     double* total_bytes) {
+  if (!f || kernel_id < 0 || kernel_id > 1) return GLM_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return GLM_EHIP;
+  for (auto& e : f->ev_used) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) return GLM_EHIP;
+    f->prof_ms[e.kid] += ms;
+    f->prof_launch[e.kid] += 1;
+    f->ev_free.push_back(e);
+  }
+  f->ev_used.clear();
+  unsigned long long hb[2] = {0, 0};
+  if (hipMemcpy(hb, f->ws + f->p.o_bytes, sizeof(hb), hipMemcpyDeviceToHost) != hipSuccess)
+    return GLM_EHIP;
+  if (launches) *launches = f->prof_launch[kernel_id];
+  if (total_ms) *total_ms = f->prof_ms[kernel_id];
+  if (total_bytes) *total_bytes = (double)hb[kernel_id];
+  // clear this kernel's counters
+  f->prof_launch[kernel_id] = 0;
+  f->prof_ms[kernel_id] = 0.0;
+  hb[kernel_id] = 0;
+  if (hipMemcpy(f->ws + f->p.o_bytes, hb, sizeof(hb), hipMemcpyHostToDevice) != hipSuccess)
+    return GLM_EHIP;
+  return GLM_OK;
+}
+
+void glm_factor_destroy(glm_factor* f) {
+  if (!f) return;
+  for (auto& e : f->ev_used) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  for (auto& e : f->ev_free) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  if (f->h_count) (void)hipHostFree(f->h_count);
+  delete f;
+}
+
+const char* glm_strerror(int code) {
+  switch (code) {
+    case GLM_OK: return "ok / converged";
+    case GLM_EINVAL: return "invalid argument or shape";
+    case GLM_EWORKSPACE: return "workspace missing or too small";
+    case GLM_EHIP: return "HIP runtime error";
+    case GLM_EUNSUPPORTED: return "shape outside the supported limits";
+    case GLM_INFO_STAGNATED: return "terminated: c_i stopped decreasing";
+    case GLM_INFO_NOCONV: return "iteration limit reached";
+    case GLM_INFO_BREAKDOWN: return "breakdown: d_i <= 0 or not finite";
+    case GLM_INFO_RANK: return "numerically rank-deficient regressor block";
+    default: return "unknown code";
+  }
+}
+
+}  // extern "C"

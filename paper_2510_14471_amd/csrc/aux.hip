@@ -1,0 +1,569 @@
+// Setup, iterative-refinement and gradient kernels around the PCG-Aug core.
+//
+//  * refinement (mixed precision): the double-precision residual of the
+//    augmented system  rho = [y - Sigma u - X beta ; h2 - X^T u]  read from X,
+//    not from the single-precision Q, then per (instance, rhs) the stopping
+//    test and the right-hand sides of the next inner solve;
+//  * gradients: dOmega = -sym(sum_t L_t U_t^T) (Kronecker-reduced outer
+//    products of the adjoint and primal u blocks) and dX_i = -(l_u,i beta_i^T
+//    + u_i l_beta,i^T), from the reverse rule of the augmented system.
+#include "glm_internal.h"
+
+#include <cmath>
+
+namespace glm {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t count, T v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// alpha_b = max_i omega_ii (D = alpha I) and, when requested, a single-precision Omega.
+__global__ void k_alpha(const InstDesc* __restrict__ insts, int B,
+                        const double* __restrict__ Om, double* __restrict__ alpha,
+                        float* __restrict__ Om32) {
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const InstDesc in = insts[b];
+  const double* o = Om + in.om_off;
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int i = 0; i < in.G; ++i) a = fmax(a, o[i * in.G + i]);
+    alpha[b] = (a > 0.0) ? a : 1.0;
+  }
+  if (Om32)
+    for (int e = threadIdx.x; e < in.G * in.G; e += blockDim.x) Om32[in.om_off + e] = (float)o[e];
+}
+
+// Fresh per-(instance, rhs) state; instances with a rank-deficient block are
+// marked and excluded.  `status0` is ST_ACTIVE or ST_IDLE.
+__global__ void k_state_init(const InstDesc* __restrict__ insts, int B,
+                             const int* __restrict__ rankflag, int rank_extra_base,
+                             const int* __restrict__ rinst_index,
+                             RhsState* __restrict__ st, int* __restrict__ inst_active,
+                             int* __restrict__ ost, int maxit_user) {
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const InstDesc in = insts[b];
+  __shared__ int bad;
+  if (threadIdx.x == 0) {
+    int r = 0;
+    for (int i = 0; i < in.G; ++i) r |= rankflag[in.blk0 + i];
+    if (in.kc > 0 && rinst_index[b] >= 0) r |= rankflag[rank_extra_base + rinst_index[b]];
+    bad = r;
+    inst_active[b] = !r;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < in.K) {
+    RhsState s;
+    s.c = s.c1 = s.d = s.lam = s.mu = s.cmin = 0.0;
+    s.rnorm2 = s.ynorm2 = 0.0;
+    s.status = bad ? ST_RANK : ST_ACTIVE;
+    s.iters = s.since = s.total_iters = 0;
+    st[in.rhs0 + threadIdx.x] = s;
+    if (ost) ost[in.rhs0 + threadIdx.x] = bad ? ST_RANK : ST_ACTIVE;
+  }
+  (void)maxit_user;
+}
+
+// Before a final projection: every instance with a solved rhs takes part.
+__global__ void k_activate(const InstDesc* __restrict__ insts, int B,
+                           const RhsState* __restrict__ st, int* __restrict__ inst_active) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const InstDesc in = insts[b];
+  int any = 0;
+  for (int k = 0; k < in.K; ++k) {
+    const int s = st[in.rhs0 + k].status;
+    any |= (s != ST_IDLE && s != ST_RANK);
+  }
+  inst_active[b] = any;
+}
+
+// restriction rows of X* h2 (bottom of the projected start) -> wc
+template <typename T>
+__global__ void k_copy_tc(const InstDesc* __restrict__ insts, int B, const T* __restrict__ Tm,
+                          double* __restrict__ wc) {
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const InstDesc in = insts[b];
+  for (int e = threadIdx.x; e < in.kc * in.K; e += blockDim.x)
+    wc[in.c_off + e] = (double)Tm[in.t_off + (int64_t)in.n * in.K + e];
+}
+
+// ---------------------------------------------------------------------------
+// double-precision refinement residual, one row tile per workgroup:
+//   rho_y = y - W Omega - [X_i beta_i]   (written in single precision for the
+//   inner solve), partial sums of ||rho_y||^2 and ||y||^2, and the partial
+//   column sums of X^T W.
+// ---------------------------------------------------------------------------
+struct ResArgs {
+  const InstDesc* __restrict__ insts;
+  const TileDesc* __restrict__ tiles;
+  const BlockDesc* __restrict__ blks;
+  const int* __restrict__ colblk;
+  const int* __restrict__ inst_active;
+  const double* __restrict__ X;
+  const double* __restrict__ Om;
+  const double* __restrict__ y;
+  const double* __restrict__ w;
+  const double* __restrict__ beta;
+  float* rho;
+  double* Tpart;
+  double* rpart;   // [tile][KMAX]  ||rho_y||^2
+  double* ypart;   // [tile][KMAX]  ||y||^2
+};
+
+template <int KC>
+__device__ void wg_reduce_store(double (&acc)[KC], int K, double* out, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    double s = wave_sum(acc[k]);
+    if (lane == 0) red[k * (NT / 64) + wv] = s;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < K) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) s += red[threadIdx.x * (NT / 64) + q];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+template <int KC, int SL>
+__global__ void __launch_bounds__(NT) k_residual(ResArgs a) {
+  const TileDesc tile = a.tiles[blockIdx.x];
+  if (!a.inst_active[tile.inst]) return;
+  const InstDesc in = a.insts[tile.inst];
+  const int G = in.G, K = in.K, n = in.n, rs = in.rs64;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Ws = reinterpret_cast<double*>(smem_raw);
+  double* Bs = Ws + (size_t)rs * G * K;
+  __shared__ double red[KC * (NT / 64)];
+  const double* __restrict__ Om = a.Om + in.om_off;
+  const double* __restrict__ Xb = a.X + in.q_off;
+  const double* __restrict__ bb = a.beta + in.b_off;
+  const int* __restrict__ cb = a.colblk + in.col_off;
+  const BlockDesc* __restrict__ bd = a.blks + in.blk0;
+  double tacc[SL][KC];
+#pragma unroll
+  for (int s = 0; s < SL; ++s)
+#pragma unroll
+    for (int k = 0; k < KC; ++k) tacc[s][k] = 0.0;
+  double racc[KC], yacc[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) racc[k] = yacc[k] = 0.0;
+  for (int sub = 0; sub < tile.rows; sub += rs) {
+    const int nr = min(rs, tile.rows - sub);
+    const int row = tile.row0 + sub;
+    const int64_t base = in.v_off + (int64_t)row * G * K;
+    const int cnt = nr * G * K;
+    for (int e = threadIdx.x; e < cnt; e += NT) Ws[e] = a.w[base + e];
+    __syncthreads();
+    for (int unit = threadIdx.x; unit < nr * G; unit += NT) {
+      const int t = unit / G, j = unit - t * G;
+      double acc[KC];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+      const double* wrow = Ws + (size_t)t * G * K;
+      for (int i = 0; i < G; ++i) {
+        const double om = Om[i * G + j];
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+          if (k < K) acc[k] += wrow[i * K + k] * om;
+      }
+#pragma unroll
+      for (int k = 0; k < KC; ++k)
+        if (k < K) Bs[((size_t)t * G + j) * K + k] = acc[k];
+    }
+    __syncthreads();
+    for (int unit = threadIdx.x; unit < nr * G; unit += NT) {
+      const int t = unit / G, i = unit - t * G;
+      const BlockDesc b = bd[i];
+      double xb[KC];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) xb[k] = 0.0;
+      const double* xrow = Xb + (int64_t)(row + t) * n + b.col;
+      const double* brow = bb + (int64_t)b.col * K;
+      for (int c = 0; c < b.ni; ++c) {
+        const double x = xrow[c];
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+          if (k < K) xb[k] += x * brow[c * K + k];
+      }
+      const int64_t e0 = base + ((int64_t)t * G + i) * K;
+      const int l0 = (t * G + i) * K;
+#pragma unroll
+      for (int k = 0; k < KC; ++k)
+        if (k < K) {
+          const double yv = a.y ? a.y[e0 + k] : 0.0;
+          const double r = yv - Bs[l0 + k] - xb[k];
+          a.rho[e0 + k] = (float)r;
+          racc[k] += r * r;
+          yacc[k] += yv * yv;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int c = threadIdx.x + s * NT;
+      if (c < n) {
+        const int bi = cb[c];
+        const double* xcol = Xb + (int64_t)row * n + c;
+        for (int t = 0; t < nr; ++t) {
+          const double x = xcol[(int64_t)t * n];
+          const double* wr = Ws + ((size_t)t * G + bi) * K;
+#pragma unroll
+          for (int k = 0; k < KC; ++k)
+            if (k < K) tacc[s][k] += x * wr[k];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* tp = a.Tpart + tile.tp_off;
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int c = threadIdx.x + s * NT;
+    if (c < n) {
+#pragma unroll
+      for (int k = 0; k < KC; ++k)
+        if (k < K) tp[(int64_t)c * K + k] = tacc[s][k];
+    }
+  }
+  wg_reduce_store<KC>(racc, K, a.rpart + (int64_t)blockIdx.x * KMAX, red);
+  wg_reduce_store<KC>(yacc, K, a.ypart + (int64_t)blockIdx.x * KMAX, red);
+}
+
+// Per instance: rho_0 = h2 - X^T w - R_c^T wc, rho_c = r - R_c beta, the norms
+// and the outer stopping test.  Rhs that still need work become ST_ACTIVE for
+// the next inner solve, the others ST_IDLE; ost keeps the outer outcome.
+__global__ void __launch_bounds__(NT)
+k_outer_check(const InstDesc* __restrict__ insts, int* __restrict__ inst_active,
+              RhsState* __restrict__ st, int* __restrict__ ost,
+              const double* __restrict__ rpart, const double* __restrict__ ypart,
+              const double* __restrict__ XtW, const double* __restrict__ h2,
+              const double* __restrict__ Rc, const double* __restrict__ rvec,
+              const double* __restrict__ beta, const double* __restrict__ wc,
+              double* __restrict__ rho0, double* __restrict__ rhoc, double tol,
+              int step, int last_step) {
+  const int b = blockIdx.x;
+  const InstDesc in = insts[b];
+  const int K = in.K, n = in.n, kc = in.kc;
+  __shared__ int s_any;
+  __shared__ double rr[NT / 64], yy[NT / 64];
+  if (threadIdx.x == 0) s_any = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = 0; k < K; ++k) {
+    const int s_idx = in.rhs0 + k;
+    const int o = ost[s_idx];
+    if (o != ST_ACTIVE) continue;   // uniform across the workgroup
+    double acc_r = 0.0, acc_y = 0.0;
+    for (int c = threadIdx.x; c < n; c += NT) {
+      const int64_t bi = in.b_off + (int64_t)c * K + k;
+      double v = (h2 ? h2[bi] : 0.0) - XtW[in.t_off + (int64_t)c * K + k];
+      for (int q = 0; q < kc; ++q)
+        v -= Rc[in.rc_off + (int64_t)q * n + c] * wc[in.c_off + (int64_t)q * K + k];
+      rho0[bi] = v;
+      acc_r += v * v;
+      if (h2) acc_y += h2[bi] * h2[bi];
+    }
+    for (int q = wv; q < kc; q += NT / 64) {
+      double s = 0.0;
+      for (int c = lane; c < n; c += 64)
+        s += Rc[in.rc_off + (int64_t)q * n + c] * beta[in.b_off + (int64_t)c * K + k];
+      s = wave_sum(s);
+      if (lane == 0) {
+        const int64_t ci = in.c_off + (int64_t)q * K + k;
+        const double rv = rvec ? rvec[ci] : 0.0;
+        rhoc[ci] = rv - s;
+      }
+    }
+    __syncthreads();
+    // restriction contributions (few rows): one thread
+    double extra_r = 0.0, extra_y = 0.0;
+    if (threadIdx.x == 0) {
+      for (int q = 0; q < kc; ++q) {
+        const int64_t ci = in.c_off + (int64_t)q * K + k;
+        const double rv = rvec ? rvec[ci] : 0.0;
+        extra_r += rhoc[ci] * rhoc[ci];
+        extra_y += rv * rv;
+      }
+      for (int p = 0; p < in.ntiles; ++p) {
+        extra_r += rpart[(int64_t)(in.tile0 + p) * KMAX + k];
+        extra_y += ypart[(int64_t)(in.tile0 + p) * KMAX + k];
+      }
+    }
+    acc_r += extra_r;
+    acc_y += extra_y;
+    acc_r = wave_sum(acc_r);
+    acc_y = wave_sum(acc_y);
+    if (lane == 0) {
+      rr[wv] = acc_r;
+      yy[wv] = acc_y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double R2 = 0.0, Y2 = 0.0;
+      for (int q = 0; q < NT / 64; ++q) {
+        R2 += rr[q];
+        Y2 += yy[q];
+      }
+      RhsState& s = st[s_idx];
+      const double prev = s.rnorm2;   // residual of the previous refinement step
+      s.rnorm2 = R2;
+      s.ynorm2 = Y2;
+      if (!(R2 > tol * tol * Y2)) {
+        ost[s_idx] = ST_CONVERGED;
+        s.status = ST_IDLE;
+      } else if (step > 0 && !(R2 < 0.25 * prev)) {
+        // the residual no longer halves: refinement has reached the accuracy
+        // the arithmetic allows (the last correction is kept)
+        ost[s_idx] = ST_STAGNATED;
+        s.status = ST_IDLE;
+      } else if (last_step || !isfinite(R2)) {
+        ost[s_idx] = ST_MAXITER;
+        s.status = ST_IDLE;
+      } else {
+        s.status = ST_ACTIVE;
+        s_any = 1;
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) inst_active[b] = s_any;
+  for (int k = threadIdx.x; k < K; k += NT) {
+    if (ost[in.rhs0 + k] != ST_ACTIVE && st[in.rhs0 + k].status == ST_ACTIVE)
+      st[in.rhs0 + k].status = ST_IDLE;
+  }
+}
+
+// u += du (single -> double) for the rhs of the inner solve, over one tile.
+__global__ void __launch_bounds__(NT)
+k_update_u(const InstDesc* __restrict__ insts, const TileDesc* __restrict__ tiles,
+           const int* __restrict__ inst_active, const RhsState* __restrict__ st,
+           const float* __restrict__ du, double* __restrict__ u) {
+  const TileDesc tile = tiles[blockIdx.x];
+  if (!inst_active[tile.inst]) return;
+  const InstDesc in = insts[tile.inst];
+  __shared__ int s_on[KMAX];
+  if ((int)threadIdx.x < in.K) {
+    const int s = st[in.rhs0 + threadIdx.x].status;
+    s_on[threadIdx.x] = (s != ST_IDLE && s != ST_RANK);
+  }
+  __syncthreads();
+  const int64_t base = in.v_off + (int64_t)tile.row0 * in.G * in.K;
+  const int cnt = tile.rows * in.G * in.K;
+  for (int e = threadIdx.x; e < cnt; e += NT)
+    if (s_on[e % in.K]) u[base + e] += (double)du[base + e];
+}
+
+__global__ void k_update_c(const InstDesc* __restrict__ insts, int B,
+                           const RhsState* __restrict__ st, const double* __restrict__ dwc,
+                           double* __restrict__ wc64) {
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const InstDesc in = insts[b];
+  for (int e = threadIdx.x; e < in.kc * in.K; e += blockDim.x) {
+    const int k = e % in.K;
+    const int s = st[in.rhs0 + k].status;
+    if (s != ST_IDLE && s != ST_RANK) wc64[in.c_off + e] += dwc[in.c_off + e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gradients
+// ---------------------------------------------------------------------------
+
+// per tile: S[i][j] = sum_{t in tile, k} L[t][i][k] U[t][j][k]  (G x G partial)
+__global__ void __launch_bounds__(NT)
+k_grad_omega_part(const InstDesc* __restrict__ insts, const TileDesc* __restrict__ tiles,
+                  const double* __restrict__ L, const double* __restrict__ U,
+                  double* __restrict__ part) {
+  const TileDesc tile = tiles[blockIdx.x];
+  const InstDesc in = insts[tile.inst];
+  const int G = in.G, K = in.K;
+  const int64_t base = in.v_off + (int64_t)tile.row0 * G * K;
+  double* out = part + tile.tp_off;
+  for (int pr = threadIdx.x; pr < G * G; pr += NT) {
+    const int i = pr / G, j = pr % G;
+    double s = 0.0;
+    for (int t = 0; t < tile.rows; ++t) {
+      const double* lr = L + base + ((int64_t)t * G + i) * K;
+      const double* ur = U + base + ((int64_t)t * G + j) * K;
+      for (int k = 0; k < K; ++k) s += lr[k] * ur[k];
+    }
+    out[pr] = s;
+  }
+}
+
+__global__ void __launch_bounds__(NT)
+k_grad_omega_reduce(const InstDesc* __restrict__ insts, const TileDesc* __restrict__ tiles,
+                    const double* __restrict__ part, double* __restrict__ dOm) {
+  const InstDesc in = insts[blockIdx.x];
+  const int G = in.G;
+  const int64_t base = tiles[in.tile0].tp_off;
+  for (int pr = threadIdx.x; pr < G * G; pr += NT) {
+    const int i = pr / G, j = pr % G;
+    double sij = 0.0, sji = 0.0;
+    for (int p = 0; p < in.ntiles; ++p) {
+      sij += part[base + (int64_t)p * in.tp_stride + i * G + j];
+      sji += part[base + (int64_t)p * in.tp_stride + j * G + i];
+    }
+    dOm[in.om_off + pr] = -0.5 * (sij + sji);
+  }
+}
+
+// dX[t][c] = -sum_k ( L[t][i(c)][k] beta[c][k] + U[t][i(c)][k] lb[c][k] )
+__global__ void __launch_bounds__(NT)
+k_grad_x(const InstDesc* __restrict__ insts, const TileDesc* __restrict__ tiles,
+         const int* __restrict__ colblk, const double* __restrict__ L,
+         const double* __restrict__ U, const double* __restrict__ beta,
+         const double* __restrict__ lb, double* __restrict__ dX) {
+  const TileDesc tile = tiles[blockIdx.x];
+  const InstDesc in = insts[tile.inst];
+  const int G = in.G, K = in.K, n = in.n;
+  const int* cb = colblk + in.col_off;
+  for (int e = threadIdx.x; e < tile.rows * n; e += NT) {
+    const int t = e / n, c = e % n;
+    const int i = cb[c];
+    const int64_t vr = in.v_off + ((int64_t)(tile.row0 + t) * G + i) * K;
+    const int64_t br = in.b_off + (int64_t)c * K;
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s += L[vr + k] * beta[br + k] + U[vr + k] * lb[br + k];
+    dX[in.q_off + (int64_t)(tile.row0 + t) * n + c] = -s;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+static unsigned grid_for(int64_t count) {
+  int64_t b = (count + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (unsigned)b;
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, int64_t count, T v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(count)), dim3(256), 0, s, p, count, v);
+  return hipGetLastError();
+}
+template hipError_t launch_fill<double>(double*, int64_t, double, hipStream_t);
+template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
+template hipError_t launch_fill<int>(int*, int64_t, int, hipStream_t);
+
+hipError_t launch_alpha(const InstDesc* insts, int B, const double* Om, double* alpha,
+                        float* Om32, hipStream_t s) {
+  hipLaunchKernelGGL(k_alpha, dim3(B), dim3(256), 0, s, insts, B, Om, alpha, Om32);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(const InstDesc* insts, int B, const int* rankflag,
+                             int rank_extra_base, const int* rinst_index, RhsState* st,
+                             int* inst_active, int* ost, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init, dim3(B), dim3(64), 0, s, insts, B, rankflag,
+                     rank_extra_base, rinst_index, st, inst_active, ost, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_activate(const InstDesc* insts, int B, const RhsState* st, int* inst_active,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_activate, dim3((B + 255) / 256), dim3(256), 0, s, insts, B, st,
+                     inst_active);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy_tc(const InstDesc* insts, int B, const T* Tm, double* wc,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_tc<T>, dim3(B), dim3(64), 0, s, insts, B, Tm, wc);
+  return hipGetLastError();
+}
+template hipError_t launch_copy_tc<double>(const InstDesc*, int, const double*, double*,
+                                           hipStream_t);
+template hipError_t launch_copy_tc<float>(const InstDesc*, int, const float*, double*,
+                                          hipStream_t);
+
+#define GLM_LAUNCH_RES(KCV, SLV)                                                          \
+  if (kc_t == KCV && sl == SLV) {                                                         \
+    hipLaunchKernelGGL((k_residual<KCV, SLV>), dim3(ntiles), dim3(NT), lds, s, a);        \
+    return hipGetLastError();                                                             \
+  }
+
+hipError_t launch_residual(const InstDesc* insts, const TileDesc* tiles, int ntiles,
+                           const BlockDesc* blks, const int* colblk, const int* inst_active,
+                           const double* X, const double* Om, const double* y,
+                           const double* w, const double* beta, float* rho, double* Tpart,
+                           double* rpart, double* ypart, int kc_t, int sl, size_t lds,
+                           hipStream_t s) {
+  ResArgs a{insts, tiles, blks, colblk, inst_active, X, Om, y, w, beta, rho, Tpart, rpart, ypart};
+  GLM_LAUNCH_RES(1, 1) GLM_LAUNCH_RES(1, 2) GLM_LAUNCH_RES(1, 3) GLM_LAUNCH_RES(1, 4)
+  GLM_LAUNCH_RES(1, 8) GLM_LAUNCH_RES(2, 1) GLM_LAUNCH_RES(2, 2) GLM_LAUNCH_RES(2, 3)
+  GLM_LAUNCH_RES(2, 4) GLM_LAUNCH_RES(2, 8) GLM_LAUNCH_RES(4, 1) GLM_LAUNCH_RES(4, 2)
+  GLM_LAUNCH_RES(4, 3) GLM_LAUNCH_RES(4, 4) GLM_LAUNCH_RES(4, 8) GLM_LAUNCH_RES(8, 1)
+  GLM_LAUNCH_RES(8, 2) GLM_LAUNCH_RES(8, 3) GLM_LAUNCH_RES(8, 4) GLM_LAUNCH_RES(16, 1)
+  GLM_LAUNCH_RES(16, 2) GLM_LAUNCH_RES(16, 3) GLM_LAUNCH_RES(16, 4)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_outer_check(const InstDesc* insts, int B, int* inst_active, RhsState* st,
+                              int* ost, const double* rpart, const double* ypart,
+                              const double* XtW, const double* h2, const double* Rc,
+                              const double* rvec, const double* beta, const double* wc,
+                              double* rho0, double* rhoc, double tol, int step,
+                              int last_step, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_check, dim3(B), dim3(NT), 0, s, insts, inst_active, st, ost,
+                     rpart, ypart, XtW, h2, Rc, rvec, beta, wc, rho0, rhoc, tol, step,
+                     last_step);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_u(const InstDesc* insts, const TileDesc* tiles, int ntiles,
+                           const int* inst_active, const RhsState* st, const float* du,
+                           double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_u, dim3(ntiles), dim3(NT), 0, s, insts, tiles, inst_active, st,
+                     du, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_c(const InstDesc* insts, int B, const RhsState* st,
+                           const double* dwc, double* wc64, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_c, dim3(B), dim3(64), 0, s, insts, B, st, dwc, wc64);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const InstDesc* insts, const TileDesc* tiles, int ntiles, int B,
+                       const int* colblk, const double* L, const double* U,
+                       const double* beta, const double* lb, double* part, double* dOm,
+                       double* dX, hipStream_t s) {
+  if (dOm) {
+    hipLaunchKernelGGL(k_grad_omega_part, dim3(ntiles), dim3(NT), 0, s, insts, tiles, L, U,
+                       part);
+    hipLaunchKernelGGL(k_grad_omega_reduce, dim3(B), dim3(NT), 0, s, insts, tiles, part, dOm);
+  }
+  if (dX)
+    hipLaunchKernelGGL(k_grad_x, dim3(ntiles), dim3(NT), 0, s, insts, tiles, colblk, L, U,
+                       beta, lb, dX);
+  return hipGetLastError();
+}
+
+}  // namespace glm

@@ -1,0 +1,169 @@
+// Internal descriptors and launch helpers shared by the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace glm {
+
+constexpr int NT = 256;          // threads per workgroup of the tile kernels
+constexpr int KMAX = 16;         // right-hand sides per instance
+constexpr int QR_NMAX = 64;      // widest block the QR kernel factors
+
+// Per-(instance, rhs) iteration status.
+enum : int {
+  ST_ACTIVE = 0,
+  ST_CONVERGED = 1,
+  ST_BREAKDOWN = 2,
+  ST_STAGNATED = 3,
+  ST_MAXITER = 4,
+  ST_RANK = 5,
+  ST_IDLE = 6,     // not part of the current (inner) solve
+};
+
+struct InstDesc {
+  int G, M, K, kc, n;
+  int blk0;        // first block (equation) index in the BlockDesc table
+  int rhs0;        // first (instance, rhs) state index
+  int tile0;       // first tile of this instance
+  int ntiles;
+  int rs;          // rows per LDS-staged sub-tile
+  int maxit;       // PCG iteration bound m - n + 1
+  int rs64;        // rows per sub-tile for the double-precision passes
+  int64_t tp_stride;  // elements per tile partial: max(n K, G G)
+  int64_t q_off;   // Q / X (M x n)
+  int64_t v_off;   // vectors (M x G x K)
+  int64_t om_off;  // Omega (G x G)
+  int64_t b_off;   // beta-like (n x K)
+  int64_t t_off;   // reduced projections ((n + kc) x K)
+  int64_t col_off; // column -> block map (n)
+  int64_t c_off;   // restriction vectors (kc x K)
+  int64_t rc_off;  // R_c (kc x n)
+  int64_t nb_off;  // null-space basis N ((n + kc) x kc)
+};
+
+struct BlockDesc {
+  int inst, eq, col, ni;
+  int64_t r_off;   // R_i (ni x ni, row-major, upper triangular)
+};
+
+struct TileDesc {
+  int inst, row0, rows, part;  // part = index of the tile within its instance
+  int64_t tp_off;              // element offset of this tile's partial projection (n x K)
+};
+
+struct QRJob {
+  int64_t a_off;   // first element of the block inside the factored array
+  int rows, cols, ld;
+  int flag;        // index into the rank-flag array
+  int64_t r_off;   // where R (cols x cols) goes, or -1
+};
+
+struct RhsState {
+  double c, c1, d, lam, mu, cmin;
+  double rnorm2, ynorm2;       // refinement residual and reference norms (mixed)
+  int status, iters, since, total_iters;
+};
+
+struct RedChunk {
+  int inst, p0;
+};
+
+// Arguments of the two projection-pass kernels (host side).
+template <typename T>
+struct PassLaunch {
+  const InstDesc* insts;
+  const TileDesc* tiles;
+  int ntiles;
+  const BlockDesc* blks;
+  const int* colblk;
+  const int* inst_active;
+  const T* Q;
+  const T* Om;
+  const double* alpha;
+  const RhsState* st;
+  const T* y;
+  T* w;
+  T* g;
+  T* u;
+  const T* Tm;
+  T* Tpart;
+  double* dpart;
+  double* cpart;
+  unsigned long long* bytes;
+  int w_nonzero;
+  int kc_t;        // K bucket (1, 2, 4, 8, 16)
+  int sl;          // column slots per thread (1, 2, 3, 4, 8)
+  size_t lds;      // dynamic LDS bytes
+};
+
+
+// ---- launchers (defined next to their kernels) ----------------------------
+hipError_t launch_qr(const QRJob* d_jobs, int njobs, int nmax, double* A, double* R,
+                     int* flags, hipStream_t s);
+hipError_t launch_to_float(const double* src, float* dst, int64_t count, hipStream_t s);
+hipError_t launch_nullbasis_input(const InstDesc* insts, const int* rinst, int nr,
+                                  const BlockDesc* blks, const double* R, const double* Rc,
+                                  double* Nb, hipStream_t s);
+template <typename T>
+hipError_t launch_pass_a(const PassLaunch<T>& p, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_pass_b(const PassLaunch<T>& p, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_reduce_t(const InstDesc* insts, const TileDesc* tiles, const int* inst_active,
+                           const void* chunks, int nchunks, const T* Tpart, T* Tm,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_scalar_a(const InstDesc* insts, const TileDesc* tiles, const int* inst_active,
+                           RhsState* st, const double* dpart, T* Tm, const double* Nb,
+                           const double* rvec, int B, int mode_iter, int do_d, hipStream_t s);
+hipError_t launch_scalar_b(const InstDesc* insts, int* inst_active, int* inst_count,
+                           RhsState* st, const double* cpart, const double* alpha,
+                           const void* Tm, int t_is_double, double* gc, double* uc,
+                           double* wc, const double* rvec, int B, int mode_iter,
+                           double tol, int stall, int maxit_cap, hipStream_t s);
+hipError_t launch_count(const int* inst_count, int B, int* out, hipStream_t s);
+template <typename TS, typename TD, bool UPPER, bool ADD>
+hipError_t launch_trisolve(const InstDesc* insts, const BlockDesc* blks, int nblk,
+                           const int* inst_active, const RhsState* st, int need_active,
+                           const double* R, const TS* src, int src_is_t, TD* dst,
+                           int dst_is_t, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* p, int64_t count, T v, hipStream_t s);
+hipError_t launch_alpha(const InstDesc* insts, int B, const double* Om, double* alpha,
+                        float* Om32, hipStream_t s);
+hipError_t launch_state_init(const InstDesc* insts, int B, const int* rankflag,
+                             int rank_extra_base, const int* rinst_index, RhsState* st,
+                             int* inst_active, int* ost, hipStream_t s);
+hipError_t launch_activate(const InstDesc* insts, int B, const RhsState* st, int* inst_active,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_copy_tc(const InstDesc* insts, int B, const T* Tm, double* wc,
+                          hipStream_t s);
+hipError_t launch_residual(const InstDesc* insts, const TileDesc* tiles, int ntiles,
+                           const BlockDesc* blks, const int* colblk, const int* inst_active,
+                           const double* X, const double* Om, const double* y,
+                           const double* w, const double* beta, float* rho, double* Tpart,
+                           double* rpart, double* ypart, int kc_t, int sl, size_t lds,
+                           hipStream_t s);
+hipError_t launch_outer_check(const InstDesc* insts, int B, int* inst_active, RhsState* st,
+                              int* ost, const double* rpart, const double* ypart,
+                              const double* XtW, const double* h2, const double* Rc,
+                              const double* rvec, const double* beta, const double* wc,
+                              double* rho0, double* rhoc, double tol, int step,
+                              int last_step, hipStream_t s);
+hipError_t launch_update_u(const InstDesc* insts, const TileDesc* tiles, int ntiles,
+                           const int* inst_active, const RhsState* st, const float* du,
+                           double* u, hipStream_t s);
+hipError_t launch_update_c(const InstDesc* insts, int B, const RhsState* st,
+                           const double* dwc, double* wc64, hipStream_t s);
+hipError_t launch_grad(const InstDesc* insts, const TileDesc* tiles, int ntiles, int B,
+                       const int* colblk, const double* L, const double* U,
+                       const double* beta, const double* lb, double* part, double* dOm,
+                       double* dX, hipStream_t s);
+
+// pass-kernel modes
+enum : int { PASS_A_ITER = 0, PASS_A_RHS = 1 };
+enum : int { PASS_B_ITER = 0, PASS_B_INIT = 1, PASS_B_EXPAND = 2 };
+
+}  // namespace glm

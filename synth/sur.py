@@ -30,6 +30,8 @@ Omega for the noise, eigenvalues to calibrate a condition number).
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -213,13 +215,19 @@ def _batch(seed, B, G_rng, M_rng, n_rng, K, shift, name, subset=None,
     n_lists = [parent.integers(n_rng[0], n_rng[1] + 1, size=int(g)).tolist()
                for g in Gs]
     children = np.random.SeedSequence(seed).spawn(B)
-    idx = range(B) if subset is None else subset
-    out = []
-    for b in idx:
+    idx = list(range(B)) if subset is None else list(subset)
+
+    def one(b):
         rng = np.random.default_rng(children[b])
         G = int(Gs[b])
         Omega = _aat_plus(rng, G, shift)
-        out.append(_instance(rng, int(Ms[b]), n_lists[b], Omega, K, intercept))
+        return _instance(rng, int(Ms[b]), n_lists[b], Omega, K, intercept)
+
+    # each instance has its own stream, so drawing them concurrently gives the
+    # same values as drawing them in order
+    workers = max(1, min(8, os.cpu_count() or 1, len(idx)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        out = list(ex.map(one, idx))
     return SURBatch(out, name=name)
 
 

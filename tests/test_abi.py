@@ -1,0 +1,94 @@
+"""The C-ABI library loads, exports every symbol include/glm.h declares, and
+its host-side logic (shape validation, workspace sizing) behaves; no device
+calls are made here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "glm.h")
+LIB = os.path.join(ROOT, "paper_2510_14471_amd", "libglm_hip.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(glm_[a-z_]+)\s*\(", src)))
+
+
+def _exported():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True,
+                         text=True, check=True).stdout
+    return {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libglm_hip.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared()
+    assert len(declared) >= 10
+    exported = _exported()
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    for s in declared:
+        getattr(lib, s)
+
+
+def test_python_binding_names_match_header():
+    from paper_2510_14471_amd import _lib
+    assert sorted(_lib.EXPORTED) == _declared()
+
+
+def _shape(G, M, K, n_flat, k=None):
+    from paper_2510_14471_amd import _lib
+    return _lib.Shape(G, M, K, n_flat, k)
+
+
+def test_shape_validation_and_workspace_sizes():
+    from paper_2510_14471_amd import _lib
+    ok = _shape([3, 2], [200, 50], [1, 4], [4, 6, 5, 2, 3])
+    assert _lib.glm_validate_shape(ok) == _lib.GLM_OK
+    w64 = _lib.glm_workspace_bytes(ok, _lib.GLM_FP64)
+    w32 = _lib.glm_workspace_bytes(ok, _lib.GLM_MIXED)
+    assert w64 > 8 * (200 * 15 + 50 * 5) and w32 > w64 // 2
+    # larger batches need more workspace, monotonically
+    big = _shape([3, 2], [400, 50], [1, 4], [4, 6, 5, 2, 3])
+    assert _lib.glm_workspace_bytes(big, _lib.GLM_FP64) > w64
+    bad = [
+        _shape([3], [200], [0], [4, 6, 5]),          # K < 1
+        _shape([3], [200], [17], [4, 6, 5]),         # K > 16
+        _shape([2], [5], [1], [6, 1]),               # n_i > M
+        _shape([1], [5], [1], [5]),                  # n >= G M (no null space)
+        _shape([2], [50], [1], [0, 3]),              # n_i < 1
+        _shape([1], [50], [1], [3], k=[4]),          # more restrictions than columns
+    ]
+    for s in bad:
+        assert _lib.glm_validate_shape(s) == _lib.GLM_EINVAL
+        assert _lib.glm_workspace_bytes(s, _lib.GLM_FP64) == 0
+    wide = _shape([1], [500], [1], [65])             # block wider than the QR kernel
+    assert _lib.glm_validate_shape(wide) == _lib.GLM_EUNSUPPORTED
+
+
+def test_strerror_is_total():
+    from paper_2510_14471_amd import _lib
+    for code in (0, -1, -2, -3, -4, 1, -10, -11, -12, 12345):
+        assert isinstance(_lib.glm_strerror(code), str) and _lib.glm_strerror(code)
+
+
+def test_workspace_for_the_batched_workload_fits_one_gpu():
+    import synth
+    from paper_2510_14471_amd import BatchLayout, _lib
+    sizes = synth.config2_sizes()
+    lay = BatchLayout([g for g, m, n in sizes], [m for g, m, n in sizes], [16] * 512,
+                      [0] * 512, [n for g, m, n in sizes])
+    for prec in (_lib.GLM_FP64, _lib.GLM_MIXED):
+        nb = _lib.glm_workspace_bytes(lay.shape(), prec)
+        assert 0 < nb < 40e9
