@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libglm_hip.so")
-SOURCES = ["qr.hip", "pcg.hip", "aux.hip", "api.hip"]
+SOURCES = ["qr.hip", "pcg.hip", "pass2.hip", "aux.hip", "api.hip"]
 ARCH = os.environ.get("GLM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -26,6 +26,10 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsBudget = 48 * 1024;  // dynamic LDS per workgroup (U and B slabs)
+constexpr size_t kV2Lds256 = 48 * 1024;   // lane-per-(i,k) passes: u, g, w, Q slabs (+ Omega)
+constexpr size_t kV2Lds512 = 72 * 1024;
+constexpr size_t kV2OmegaLds = 80 * 1024; // largest Omega staged in LDS
+constexpr int kV2RowsPerLane = 16;        // rows per lane and sub-tile
 constexpr int kTargetTiles = 2048;        // row tiles over the whole batch
 constexpr int kMinTileRows = 64;          // keeps the per-tile partial sums small
 constexpr int kPollEvery = 8;             // iterations between host convergence polls
@@ -62,6 +66,7 @@ struct Plan {
           sumCK = 0, sumTp = 0, sumRc = 0;
   int nrhs = 0, ntiles = 0, nblk = 0, maxK = 0, maxn = 0, maxni = 0, maxkc = 0;
   int kc_t = 1, sl = 1;
+  int v2 = 0, ntw = 256, gr = 0, nim = 8;
   size_t lds_inner = 0, lds64 = 0;
   // byte offsets inside the workspace
   size_t o_Q64, o_Q32, o_R, o_Nb, o_colblk, o_inst, o_blk, o_tile, o_qrs, o_qrn, o_chunks,
@@ -114,6 +119,23 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p) {
   int64_t sum_rows = 0;
   for (int b = 0; b < p.B; ++b) sum_rows += s->M[b];
   int rc_rows = (int)std::max<int64_t>(kMinTileRows, (sum_rows + kTargetTiles - 1) / kTargetTiles);
+  // projection-pass flavour for the whole batch
+  {
+    int maxP = 0, maxG = 0, maxni = 0;
+    int64_t off = 0;
+    for (int b = 0; b < p.B; ++b) {
+      maxP = std::max(maxP, s->G[b] * s->K[b]);
+      maxG = std::max(maxG, s->G[b]);
+      for (int i = 0; i < s->G[b]; ++i) maxni = std::max(maxni, s->n[off + i]);
+      off += s->G[b];
+    }
+    const bool om_fits = maxG <= 32 || (size_t)maxG * maxG * sv <= kV2OmegaLds;
+    p.v2 = (maxP <= 512 && om_fits) ? 1 : 0;
+    p.ntw = maxP <= 256 ? 256 : 512;
+    p.gr = maxG <= 8 ? 8 : maxG <= 16 ? 16 : maxG <= 32 ? 32 : 0;
+    p.nim = maxni <= 8 ? 8 : maxni <= 16 ? 16 : maxni <= 24 ? 24 : maxni <= 32 ? 32 : 64;
+  }
+  bool v2_fits = true;
   int64_t noff = 0;
   for (int b = 0; b < p.B; ++b) {
     InstDesc in{};
@@ -137,10 +159,25 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p) {
     in.nb_off = p.sumNb;
     in.maxit = (int)std::min<int64_t>((int64_t)in.G * in.M + in.kc - n + 1, 1 << 30);
     const size_t per_row = 2 * (size_t)in.G * in.K;
-    in.rs = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * sv)));
     in.rs64 = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * 8)));
-    p.lds_inner = std::max(p.lds_inner, per_row * sv * in.rs);
     p.lds64 = std::max(p.lds64, per_row * 8 * in.rs64);
+    if (p.v2) {
+      const size_t P = (size_t)in.G * in.K;
+      const size_t om = (p.gr == 0) ? (size_t)in.G * in.G * sv : 0;
+      in.rpar = std::max(1, p.ntw / (int)P);
+      // rows per sub-tile: the staged slabs (Q rows and three vector slabs of
+      // pass B) must fit the per-thread register buffer of the stager
+      const size_t ept = (sv == 8) ? 16 : 32;
+      const size_t slots = (size_t)p.ntw * ept;
+      const size_t rows_fit = slots / (3 * P + n);
+      if (rows_fit < 1) v2_fits = false;
+      in.rs = (int)std::max<size_t>(1, std::min<size_t>(rows_fit, (size_t)in.rpar * kV2RowsPerLane));
+      p.lds_inner = std::max(p.lds_inner, slots * sv + om);
+    } else {
+      in.rs = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * sv)));
+      in.rpar = 1;
+      p.lds_inner = std::max(p.lds_inner, per_row * sv * in.rs);
+    }
     // blocks
     int col = 0;
     for (int i = 0; i < in.G; ++i) {
@@ -170,7 +207,7 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p) {
     int step = std::max(in.rs, in.rs64);
     int trows = std::max(step, (rc_rows + step - 1) / step * step);
     in.tile0 = (int)p.tile.size();
-    in.tp_stride = std::max<int64_t>((int64_t)n * in.K, (int64_t)in.G * in.G);
+    in.tp_stride = std::max<int64_t>((int64_t)in.rpar * n * in.K, (int64_t)in.G * in.G);
     int part = 0;
     for (int r0 = 0; r0 < in.M; r0 += trows) {
       TileDesc td{};
@@ -212,6 +249,7 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p) {
     p.maxn = std::max(p.maxn, n);
     p.inst.push_back(in);
   }
+  if (p.v2 && !v2_fits) return GLM_EUNSUPPORTED;   // a row of slabs exceeds the stager
   p.nblk = (int)p.blk.size();
   p.ntiles = (int)p.tile.size();
   for (size_t r = 0; r < p.qr_nb.size(); ++r) p.qr_nb[r].flag = p.nblk + (int)r;
@@ -346,7 +384,11 @@ PassLaunch<T> pass_args(glm_factor* f, const T* Q, const T* Om, const T* y, T* w
   a.w_nonzero = 0;
   a.kc_t = p.kc_t;
   a.sl = p.sl;
-  a.lds = (sizeof(T) == 8) ? p.lds64 : p.lds_inner;
+  a.lds = (sizeof(T) == 8 && p.prec == GLM_MIXED) ? p.lds64 : p.lds_inner;
+  a.v2 = p.v2;
+  a.ntw = p.ntw;
+  a.gr = p.gr;
+  a.nim = p.nim;
   return a;
 }
 
@@ -361,7 +403,7 @@ int run_pass_a(glm_factor* f, PassLaunch<T> a, int mode, hipStream_t s) {
   } else {
     a.bytes = nullptr;
   }
-  GLM_CHECK(launch_pass_a<T>(a, mode, s));
+  GLM_CHECK(a.v2 ? launch_pass_a2<T>(a, mode, s) : launch_pass_a<T>(a, mode, s));
   ++f->launches;
   if (timed) {
     GLM_CHECK(hipEventRecord(e.b, s));
@@ -381,7 +423,7 @@ int run_pass_b(glm_factor* f, PassLaunch<T> a, int mode, hipStream_t s) {
   } else {
     a.bytes = nullptr;
   }
-  GLM_CHECK(launch_pass_b<T>(a, mode, s));
+  GLM_CHECK(a.v2 ? launch_pass_b2<T>(a, mode, s) : launch_pass_b<T>(a, mode, s));
   ++f->launches;
   if (timed) {
     GLM_CHECK(hipEventRecord(e.b, s));
@@ -400,7 +442,7 @@ int project_rhs(glm_factor* f, const T* Q, const T* Om, const T* y, T* w, bool w
   if (int rc = run_pass_a<T>(f, a, PASS_A_RHS, s)) return rc;
   GLM_CHECK(launch_reduce_t<T>(f->d_inst(), f->d_tile(), f->d_active(),
                                f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
-                               f->at<T>(p.o_Tpart), f->at<T>(p.o_Tm), s));
+                               f->at<T>(p.o_Tpart), f->at<T>(p.o_Tm), p.v2, s));
   GLM_CHECK(launch_scalar_a<T>(f->d_inst(), f->d_tile(), f->d_active(), f->d_st(),
                                f->at<double>(p.o_dpart), f->at<T>(p.o_Tm),
                                f->at<double>(p.o_Nb), rvec, p.B, 0, 0, s));
@@ -471,7 +513,7 @@ int core_solve(glm_factor* f, const T* Q, const T* Om, const T* y, const double*
     if (int rc = run_pass_a<T>(f, aa, PASS_A_ITER, s)) return rc;
     GLM_CHECK(launch_reduce_t<T>(f->d_inst(), f->d_tile(), f->d_active(),
                                  f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
-                                 f->at<T>(p.o_Tpart), Tm, s));
+                                 f->at<T>(p.o_Tpart), Tm, p.v2, s));
     GLM_CHECK(launch_scalar_a<T>(f->d_inst(), f->d_tile(), f->d_active(), f->d_st(),
                                  f->at<double>(p.o_dpart), Tm, f->at<double>(p.o_Nb),
                                  nullptr, p.B, 1, 1, s));
@@ -580,7 +622,7 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
                                 p.sl, p.lds64, s));
       GLM_CHECK(launch_reduce_t<double>(f->d_inst(), f->d_tile(), f->d_active(),
                                         f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
-                                        f->at<double>(p.o_Tpart), f->at<double>(p.o_Tm), s));
+                                        f->at<double>(p.o_Tpart), f->at<double>(p.o_Tm), 0, s));
       GLM_CHECK(launch_outer_check(f->d_inst(), p.B, f->d_active(), f->d_st(),
                                    f->at<int>(p.o_ost), f->at<double>(p.o_cpart),
                                    f->at<double>(p.o_dpart), f->at<double>(p.o_Tm), h2, f->Rc,

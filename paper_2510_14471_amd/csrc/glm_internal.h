@@ -29,8 +29,10 @@ struct InstDesc {
   int ntiles;
   int rs;          // rows per LDS-staged sub-tile
   int maxit;       // PCG iteration bound m - n + 1
-  int rs64;        // rows per sub-tile for the double-precision passes
-  int64_t tp_stride;  // elements per tile partial: max(n K, G G)
+  int rs64;        // rows per sub-tile for the double-precision residual pass
+  int rpar;        // row groups per workgroup in the lane-per-(i, k) passes
+  int pad2;
+  int64_t tp_stride;  // elements per tile partial: max(rpar n K, G G)
   int64_t q_off;   // Q / X (M x n)
   int64_t v_off;   // vectors (M x G x K)
   int64_t om_off;  // Omega (G x G)
@@ -95,6 +97,10 @@ struct PassLaunch {
   int kc_t;        // K bucket (1, 2, 4, 8, 16)
   int sl;          // column slots per thread (1, 2, 3, 4, 8)
   size_t lds;      // dynamic LDS bytes
+  int v2;          // lane-per-(i, k) passes (otherwise the column-slot passes)
+  int ntw;         // v2: threads per workgroup (256 or 512)
+  int gr;          // v2: Omega column held in registers up to this G (0: from LDS)
+  int nim;         // v2: bound on n_i (8, 16, 32, 64)
 };
 
 
@@ -110,9 +116,13 @@ hipError_t launch_pass_a(const PassLaunch<T>& p, int mode, hipStream_t s);
 template <typename T>
 hipError_t launch_pass_b(const PassLaunch<T>& p, int mode, hipStream_t s);
 template <typename T>
+hipError_t launch_pass_a2(const PassLaunch<T>& p, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_pass_b2(const PassLaunch<T>& p, int mode, hipStream_t s);
+template <typename T>
 hipError_t launch_reduce_t(const InstDesc* insts, const TileDesc* tiles, const int* inst_active,
                            const void* chunks, int nchunks, const T* Tpart, T* Tm,
-                           hipStream_t s);
+                           int use_rpar, hipStream_t s);
 template <typename T>
 hipError_t launch_scalar_a(const InstDesc* insts, const TileDesc* tiles, const int* inst_active,
                            RhsState* st, const double* dpart, T* Tm, const double* Nb,

@@ -362,7 +362,7 @@ template <typename T>
 __global__ void __launch_bounds__(NT)
 k_reduce_t(const InstDesc* __restrict__ insts, const TileDesc* __restrict__ tiles,
            const int* __restrict__ inst_active, const RedChunk* __restrict__ chunks,
-           const T* __restrict__ Tpart, T* __restrict__ Tm) {
+           const T* __restrict__ Tpart, T* __restrict__ Tm, int use_rpar) {
   const RedChunk ch = chunks[blockIdx.x];
   if (!inst_active[ch.inst]) return;
   const InstDesc in = insts[ch.inst];
@@ -370,17 +370,20 @@ k_reduce_t(const InstDesc* __restrict__ insts, const TileDesc* __restrict__ tile
   const int pr = ch.p0 + threadIdx.x;
   if (pr >= nk) return;
   const int64_t base = tiles[in.tile0].tp_off;
+  const int slots = use_rpar ? in.rpar : 1;   // row-group partials inside a tile
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  const T* src = Tpart + base + pr;
   const int64_t st4 = in.tp_stride;
-  int p = 0;
-  for (; p + 4 <= in.ntiles; p += 4) {
-    s0 += (double)src[(int64_t)p * st4];
-    s1 += (double)src[(int64_t)(p + 1) * st4];
-    s2 += (double)src[(int64_t)(p + 2) * st4];
-    s3 += (double)src[(int64_t)(p + 3) * st4];
+  for (int r = 0; r < slots; ++r) {
+    const T* src = Tpart + base + (int64_t)r * nk + pr;
+    int p = 0;
+    for (; p + 4 <= in.ntiles; p += 4) {
+      s0 += (double)src[(int64_t)p * st4];
+      s1 += (double)src[(int64_t)(p + 1) * st4];
+      s2 += (double)src[(int64_t)(p + 2) * st4];
+      s3 += (double)src[(int64_t)(p + 3) * st4];
+    }
+    for (; p < in.ntiles; ++p) s0 += (double)src[(int64_t)p * st4];
   }
-  for (; p < in.ntiles; ++p) s0 += (double)src[(int64_t)p * st4];
   Tm[in.t_off + pr] = (T)((s0 + s1) + (s2 + s3));
 }
 
@@ -678,10 +681,10 @@ hipError_t launch_pass_b(const PassLaunch<T>& p, int mode, hipStream_t s) {
 template <typename T>
 hipError_t launch_reduce_t(const InstDesc* insts, const TileDesc* tiles, const int* inst_active,
                            const void* chunks, int nchunks, const T* Tpart, T* Tm,
-                           hipStream_t s) {
+                           int use_rpar, hipStream_t s) {
   if (nchunks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_t<T>, dim3(nchunks), dim3(NT), 0, s, insts, tiles, inst_active,
-                     (const RedChunk*)chunks, Tpart, Tm);
+                     (const RedChunk*)chunks, Tpart, Tm, use_rpar);
   return hipGetLastError();
 }
 
@@ -730,10 +733,10 @@ template hipError_t launch_pass_a<float>(const PassLaunch<float>&, int, hipStrea
 template hipError_t launch_pass_b<double>(const PassLaunch<double>&, int, hipStream_t);
 template hipError_t launch_pass_b<float>(const PassLaunch<float>&, int, hipStream_t);
 template hipError_t launch_reduce_t<double>(const InstDesc*, const TileDesc*, const int*,
-                                            const void*, int, const double*, double*,
+                                            const void*, int, const double*, double*, int,
                                             hipStream_t);
 template hipError_t launch_reduce_t<float>(const InstDesc*, const TileDesc*, const int*,
-                                           const void*, int, const float*, float*,
+                                           const void*, int, const float*, float*, int,
                                            hipStream_t);
 template hipError_t launch_scalar_a<double>(const InstDesc*, const TileDesc*, const int*,
                                             RhsState*, const double*, double*, const double*,
