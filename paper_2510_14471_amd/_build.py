@@ -12,7 +12,16 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libglm_hip.so")
-SOURCES = ["qr.hip", "pcg.hip", "pass2.hip", "aux.hip", "api.hip"]
+# (source, object name, extra flags): the projection passes are compiled
+# once per precision
+SOURCES = [
+    ("qr.hip", "qr.o", []),
+    ("pcg.hip", "pcg.o", []),
+    ("proj.hip", "proj_f32.o", ["-DGLM_PROJ_T=float"]),
+    ("proj.hip", "proj_f64.o", ["-DGLM_PROJ_T=double"]),
+    ("aux.hip", "aux.o", []),
+    ("api.hip", "api.o", []),
+]
 ARCH = os.environ.get("GLM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -36,9 +45,10 @@ def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
 
-    def compile_one(src):
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [hipcc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+    def compile_one(entry):
+        src, objname, extra = entry
+        obj = os.path.join(objdir, objname)
+        cmd = [hipcc, *flags(), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{res.stderr}")

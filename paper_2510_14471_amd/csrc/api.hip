@@ -26,10 +26,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsBudget = 48 * 1024;  // dynamic LDS per workgroup (U and B slabs)
-constexpr size_t kV2Lds256 = 48 * 1024;   // lane-per-(i,k) passes: u, g, w, Q slabs (+ Omega)
-constexpr size_t kV2Lds512 = 72 * 1024;
-constexpr size_t kV2OmegaLds = 80 * 1024; // largest Omega staged in LDS
-constexpr int kV2RowsPerLane = 16;        // rows per lane and sub-tile
+constexpr size_t kRowOmegaLds = 64 * 1024; // largest Omega the row-vector passes stage in LDS
+constexpr int kRowsPerLane = 16;            // row-vector passes: rows per lane and sub-tile
 constexpr int kTargetTiles = 2048;        // row tiles over the whole batch
 constexpr int kMinTileRows = 64;          // keeps the per-tile partial sums small
 constexpr int kPollEvery = 8;             // iterations between host convergence polls
@@ -66,7 +64,7 @@ struct Plan {
           sumCK = 0, sumTp = 0, sumRc = 0;
   int nrhs = 0, ntiles = 0, nblk = 0, maxK = 0, maxn = 0, maxni = 0, maxkc = 0;
   int kc_t = 1, sl = 1;
-  int v2 = 0, ntw = 256, gr = 0, nim = 8;
+  int rowpass = 0, kv = 1, ks = 0, gr = 0, nim = 8;
   size_t lds_inner = 0, lds64 = 0;
   // byte offsets inside the workspace
   size_t o_Q64, o_Q32, o_R, o_Nb, o_colblk, o_inst, o_blk, o_tile, o_qrs, o_qrn, o_chunks,
@@ -109,7 +107,7 @@ int validate(const glm_shape* s) {
   return GLM_OK;
 }
 
-int make_plan(const glm_shape* s, glm_precision prec, Plan& p) {
+int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow_rows = true) {
   int rc = validate(s);
   if (rc != GLM_OK) return rc;
   p = Plan();
@@ -119,23 +117,41 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p) {
   int64_t sum_rows = 0;
   for (int b = 0; b < p.B; ++b) sum_rows += s->M[b];
   int rc_rows = (int)std::max<int64_t>(kMinTileRows, (sum_rows + kTargetTiles - 1) / kTargetTiles);
-  // projection-pass flavour for the whole batch
+  // projection-pass flavour for the whole batch: the row-vector passes when
+  // every instance fits them, else the column-slot passes
   {
-    int maxP = 0, maxG = 0, maxni = 0;
+    const int words = (int)(sv / 4);
+    int maxG = 0, maxni = 0;
+    bool k_div[5] = {true, true, true, true, true};   // K % 1, 2, 4 == 0
+    bool all16 = true;
     int64_t off = 0;
     for (int b = 0; b < p.B; ++b) {
-      maxP = std::max(maxP, s->G[b] * s->K[b]);
       maxG = std::max(maxG, s->G[b]);
       for (int i = 0; i < s->G[b]; ++i) maxni = std::max(maxni, s->n[off + i]);
       off += s->G[b];
+      k_div[2] = k_div[2] && s->K[b] % 2 == 0;
+      k_div[4] = k_div[4] && s->K[b] % 4 == 0;
+      all16 = all16 && s->K[b] == 16;
     }
-    const bool om_fits = maxG <= 32 || (size_t)maxG * maxG * sv <= kV2OmegaLds;
-    p.v2 = (maxP <= 512 && om_fits) ? 1 : 0;
-    p.ntw = maxP <= 256 ? 256 : 512;
-    p.gr = maxG <= 8 ? 8 : maxG <= 16 ? 16 : maxG <= 32 ? 32 : 0;
     p.nim = maxni <= 8 ? 8 : maxni <= 16 ? 16 : maxni <= 24 ? 24 : maxni <= 32 ? 32 : 64;
+    p.kv = 1;
+    for (int kv = (sv == 4) ? 4 : 2; kv > 1; kv /= 2)
+      if (k_div[kv] && p.nim * kv * words <= kProjSliceRegs) {
+        p.kv = kv;
+        break;
+      }
+    p.ks = (all16 && p.kv == ((sv == 4) ? 4 : 2)) ? 16 : 0;
+    // the Omega column in registers next to the projection slice, else in LDS
+    p.gr = (maxG <= 32 && (32 + p.nim * p.kv) * words <= kProjSliceRegs) ? 32 : 0;
+    bool fits = p.nim * words <= kProjSliceRegs;
+    if (p.gr == 0) fits = fits && (size_t)maxG * maxG * sv <= kRowOmegaLds;
+    for (int b = 0; b < p.B; ++b) fits = fits && s->G[b] * s->K[b] / p.kv <= PROJ_NT;
+    p.rowpass = (fits && allow_rows) ? 1 : 0;
+    if (p.rowpass)
+      p.lds_inner = ((size_t)PROJ_NT * (PROJ_NV * p.kv + PROJ_NQ) + PROJ_QPAD) * sv +
+                    (p.gr == 0 ? (size_t)maxG * maxG * sv : 0);
   }
-  bool v2_fits = true;
+  bool rows_fit_all = true;
   int64_t noff = 0;
   for (int b = 0; b < p.B; ++b) {
     InstDesc in{};
@@ -144,7 +160,10 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p) {
     in.K = s->K[b];
     in.kc = s->k ? s->k[b] : 0;
     int n = 0;
-    for (int i = 0; i < in.G; ++i) n += s->n[noff + i];
+    for (int i = 0; i < in.G; ++i) {
+      n += s->n[noff + i];
+      in.nimax = std::max(in.nimax, s->n[noff + i]);
+    }
     in.n = n;
     in.blk0 = (int)p.blk.size();
     in.rhs0 = p.nrhs;
@@ -161,18 +180,17 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p) {
     const size_t per_row = 2 * (size_t)in.G * in.K;
     in.rs64 = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * 8)));
     p.lds64 = std::max(p.lds64, per_row * 8 * in.rs64);
-    if (p.v2) {
-      const size_t P = (size_t)in.G * in.K;
-      const size_t om = (p.gr == 0) ? (size_t)in.G * in.G * sv : 0;
-      in.rpar = std::max(1, p.ntw / (int)P);
-      // rows per sub-tile: the staged slabs (Q rows and three vector slabs of
-      // pass B) must fit the per-thread register buffer of the stager
-      const size_t ept = (sv == 8) ? 16 : 32;
-      const size_t slots = (size_t)p.ntw * ept;
-      const size_t rows_fit = slots / (3 * P + n);
-      if (rows_fit < 1) v2_fits = false;
-      in.rs = (int)std::max<size_t>(1, std::min<size_t>(rows_fit, (size_t)in.rpar * kV2RowsPerLane));
-      p.lds_inner = std::max(p.lds_inner, slots * sv + om);
+    if (p.rowpass) {
+      const int P = in.G * in.K;
+      in.rpar = PROJ_NT / (P / p.kv);
+      // rows per sub-tile: the three vector slabs of pass B and the Q rows
+      // must fit the stager's per-thread registers
+      const int rows_v = PROJ_NV * PROJ_NT * p.kv / (3 * P);
+      const int rows_q = PROJ_NQ * PROJ_NT / n;
+      int rs = std::min(std::min(rows_v, rows_q), in.rpar * kRowsPerLane);
+      if (rs < 1) rows_fit_all = false;
+      if (rs >= in.rpar) rs = rs / in.rpar * in.rpar;   // whole rows per row group
+      in.rs = std::max(rs, 1);
     } else {
       in.rs = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * sv)));
       in.rpar = 1;
@@ -249,7 +267,10 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p) {
     p.maxn = std::max(p.maxn, n);
     p.inst.push_back(in);
   }
-  if (p.v2 && !v2_fits) return GLM_EUNSUPPORTED;   // a row of slabs exceeds the stager
+  if (p.rowpass && !rows_fit_all) {
+    // a row of slabs exceeds the stager: plan again with the column-slot passes
+    return make_plan(s, prec, p, false);
+  }
   p.nblk = (int)p.blk.size();
   p.ntiles = (int)p.tile.size();
   for (size_t r = 0; r < p.qr_nb.size(); ++r) p.qr_nb[r].flag = p.nblk + (int)r;
@@ -385,8 +406,9 @@ PassLaunch<T> pass_args(glm_factor* f, const T* Q, const T* Om, const T* y, T* w
   a.kc_t = p.kc_t;
   a.sl = p.sl;
   a.lds = (sizeof(T) == 8 && p.prec == GLM_MIXED) ? p.lds64 : p.lds_inner;
-  a.v2 = p.v2;
-  a.ntw = p.ntw;
+  a.rowpass = p.rowpass;
+  a.kv = p.kv;
+  a.ks = p.ks;
   a.gr = p.gr;
   a.nim = p.nim;
   return a;
@@ -403,7 +425,7 @@ int run_pass_a(glm_factor* f, PassLaunch<T> a, int mode, hipStream_t s) {
   } else {
     a.bytes = nullptr;
   }
-  GLM_CHECK(a.v2 ? launch_pass_a2<T>(a, mode, s) : launch_pass_a<T>(a, mode, s));
+  GLM_CHECK(a.rowpass ? launch_proj<T>(a, true, mode, s) : launch_pass_a<T>(a, mode, s));
   ++f->launches;
   if (timed) {
     GLM_CHECK(hipEventRecord(e.b, s));
@@ -423,7 +445,7 @@ int run_pass_b(glm_factor* f, PassLaunch<T> a, int mode, hipStream_t s) {
   } else {
     a.bytes = nullptr;
   }
-  GLM_CHECK(a.v2 ? launch_pass_b2<T>(a, mode, s) : launch_pass_b<T>(a, mode, s));
+  GLM_CHECK(a.rowpass ? launch_proj<T>(a, false, mode, s) : launch_pass_b<T>(a, mode, s));
   ++f->launches;
   if (timed) {
     GLM_CHECK(hipEventRecord(e.b, s));
@@ -442,7 +464,7 @@ int project_rhs(glm_factor* f, const T* Q, const T* Om, const T* y, T* w, bool w
   if (int rc = run_pass_a<T>(f, a, PASS_A_RHS, s)) return rc;
   GLM_CHECK(launch_reduce_t<T>(f->d_inst(), f->d_tile(), f->d_active(),
                                f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
-                               f->at<T>(p.o_Tpart), f->at<T>(p.o_Tm), p.v2, s));
+                               f->at<T>(p.o_Tpart), f->at<T>(p.o_Tm), p.rowpass, s));
   GLM_CHECK(launch_scalar_a<T>(f->d_inst(), f->d_tile(), f->d_active(), f->d_st(),
                                f->at<double>(p.o_dpart), f->at<T>(p.o_Tm),
                                f->at<double>(p.o_Nb), rvec, p.B, 0, 0, s));
@@ -513,7 +535,7 @@ int core_solve(glm_factor* f, const T* Q, const T* Om, const T* y, const double*
     if (int rc = run_pass_a<T>(f, aa, PASS_A_ITER, s)) return rc;
     GLM_CHECK(launch_reduce_t<T>(f->d_inst(), f->d_tile(), f->d_active(),
                                  f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
-                                 f->at<T>(p.o_Tpart), Tm, p.v2, s));
+                                 f->at<T>(p.o_Tpart), Tm, p.rowpass, s));
     GLM_CHECK(launch_scalar_a<T>(f->d_inst(), f->d_tile(), f->d_active(), f->d_st(),
                                  f->at<double>(p.o_dpart), Tm, f->at<double>(p.o_Nb),
                                  nullptr, p.B, 1, 1, s));

@@ -30,8 +30,8 @@ struct InstDesc {
   int rs;          // rows per LDS-staged sub-tile
   int maxit;       // PCG iteration bound m - n + 1
   int rs64;        // rows per sub-tile for the double-precision residual pass
-  int rpar;        // row groups per workgroup in the lane-per-(i, k) passes
-  int pad2;
+  int rpar;        // row groups per workgroup of the row-vector passes
+  int nimax;       // largest n_i of the instance
   int64_t tp_stride;  // elements per tile partial: max(rpar n K, G G)
   int64_t q_off;   // Q / X (M x n)
   int64_t v_off;   // vectors (M x G x K)
@@ -97,11 +97,21 @@ struct PassLaunch {
   int kc_t;        // K bucket (1, 2, 4, 8, 16)
   int sl;          // column slots per thread (1, 2, 3, 4, 8)
   size_t lds;      // dynamic LDS bytes
-  int v2;          // lane-per-(i, k) passes (otherwise the column-slot passes)
-  int ntw;         // v2: threads per workgroup (256 or 512)
-  int gr;          // v2: Omega column held in registers up to this G (0: from LDS)
-  int nim;         // v2: bound on n_i (8, 16, 32, 64)
+  int rowpass;     // row-vector passes (otherwise the column-slot passes)
+  int kv;          // row-vector passes: right-hand sides per lane (1, 2, 4)
+  int ks;          // row-vector passes: 16 when every instance has K = 16, else 0
+  int gr;          // row-vector passes: Omega column in registers up to this G (0: LDS)
+  int nim;         // row-vector passes: bound on n_i (8, 16, 24, 32, 64)
 };
+
+// Row-vector projection passes: workgroup size, per-thread staging capacity
+// (vector chunks of kv elements, Q scalars) and the register budget of the
+// per-lane projection slice (n_i bound x kv x 32-bit words per element).
+constexpr int PROJ_NT = 256;
+constexpr int PROJ_NV = 8;
+constexpr int PROJ_NQ = 8;
+constexpr int PROJ_QPAD = QR_NMAX;   // zeros after the staged Q rows
+constexpr int kProjSliceRegs = 128;
 
 
 // ---- launchers (defined next to their kernels) ----------------------------
@@ -116,9 +126,7 @@ hipError_t launch_pass_a(const PassLaunch<T>& p, int mode, hipStream_t s);
 template <typename T>
 hipError_t launch_pass_b(const PassLaunch<T>& p, int mode, hipStream_t s);
 template <typename T>
-hipError_t launch_pass_a2(const PassLaunch<T>& p, int mode, hipStream_t s);
-template <typename T>
-hipError_t launch_pass_b2(const PassLaunch<T>& p, int mode, hipStream_t s);
+hipError_t launch_proj(const PassLaunch<T>& p, bool pass_a, int mode, hipStream_t s);
 template <typename T>
 hipError_t launch_reduce_t(const InstDesc* insts, const TileDesc* tiles, const int* inst_active,
                            const void* chunks, int nchunks, const T* Tpart, T* Tm,
