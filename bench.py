@@ -24,6 +24,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SUR GLS solves/s: batched mixed-prec vs plain FP64 PCG at ≤1e-10 rel err"
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the projection passes measured with rocprofv3 counters
+# (FETCH_SIZE, WRITE_SIZE, calibrated against a plain copy kernel); valid only
+# for the kernel sources it was taken from
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_proj_sur_batch512_k16.json")
+KERNEL_SOURCES = ["paper_2510_14471_amd/csrc/proj.hip", "paper_2510_14471_amd/csrc/api.hip",
+                  "paper_2510_14471_amd/csrc/glm_internal.h"]
+PASS_NAMES = {0: "k_proj_a<float> (pass A: u <- g + mu u, B = U Omega, d = u.B, T += Q^T B)",
+              1: "k_proj_b<float> (pass B: g -= (lambda/alpha)(B - Q T), w -= lambda u, c = g.g)"}
 
 
 def log(msg):
@@ -160,12 +168,12 @@ def main():
     if prof:
         kid = max((0, 1), key=lambda k: prof[k][1])
         n_l, ms, by = prof[kid]
-        names = {0: "k_pass_a<float> (u <- g + mu u, Sigma u, d, Q^T Sigma u)",
-                 1: "k_pass_b<float> (Sigma u - Q T, g, w updates, c)"}
+        names = PASS_NAMES
         ach = (by / n_l) / (ms / n_l * 1e-3) / 1e9 if n_l and ms > 0 else 0.0
         out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                           "traffic": None, "kernel": names[kid], "launches": n_l,
+                           "traffic": measured_traffic(kid), "kernel": names[kid],
+                           "launches": n_l,
                            "avg_us": round(1000 * ms / max(n_l, 1), 2),
                            "alg_bytes_per_launch": round(by / max(n_l, 1))}
         other = 1 - kid
@@ -176,6 +184,29 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel_path in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel_path), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(pass_id):
+    """HBM bytes per launch of the timed pass from the committed counter
+    summary, or None when it is missing or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    k = t.get("passes", {}).get(str(pass_id))
+    return None if k is None else k.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(insts, budget_s):

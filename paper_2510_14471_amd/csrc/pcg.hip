@@ -348,7 +348,7 @@ k_pass_b(VecArgs<T> a) {
     wg_reduce_store<KC>(cacc, K, a.cpart + (int64_t)blockIdx.x * KMAX, red);
   if (MODE == B_ITER && a.bytes && threadIdx.x == 0) {
     const unsigned long long bq = (unsigned long long)tile.rows * n * sizeof(T);
-    const unsigned long long bv = 5ull * tile.rows * G * kact * sizeof(T);
+    const unsigned long long bv = 3ull * tile.rows * G * kact * sizeof(T);  // Q + read w, write g, w
     atomicAdd(a.bytes, bq + bv);
   }
 }

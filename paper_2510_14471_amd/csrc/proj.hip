@@ -398,13 +398,17 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
         Vec<T, KV> x;
 #pragma unroll
         for (int v = 0; v < KV; ++v) x.v[v] = tacc[c][v];
-        vstore<T, KV>(tp + (int64_t)c * K, x);
+        gstore<T, KV>(tp + (int64_t)c * K, x);
       }
   }
   if (MODE == PASS_A_ITER) {
     reduce_k<KV>(dacc, on, K, KQ, reinterpret_cast<double*>(smem_raw), dsum);
     if ((int)threadIdx.x < K) a.dpart[(int64_t)blockIdx.x * KMAX + threadIdx.x] = dsum[threadIdx.x];
   }
+  // Algorithmic bytes of one iteration: Q twice (once per pass) and each of
+  // g, u, w read and written once; pass A is charged Q + (read u, g, write u),
+  // pass B Q + (read w, write g, w).  Its reads of u and g re-read vectors
+  // pass A already moved and are not counted.  Active right-hand sides only.
   if (a.bytes && threadIdx.x == 0 && MODE == PASS_A_ITER) {
     const unsigned long long bq = (unsigned long long)tile.rows * n * sizeof(T);
     const unsigned long long bv = 3ull * tile.rows * G * kact * sizeof(T);
@@ -608,9 +612,10 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
     reduce_k<KV>(cacc, on, K, KQ, reinterpret_cast<double*>(smem_raw), csum);
     if ((int)threadIdx.x < K) a.cpart[(int64_t)blockIdx.x * KMAX + threadIdx.x] = csum[threadIdx.x];
   }
+  // algorithmic bytes: Q + (read w, write g, w); see pass A
   if (MODE == PASS_B_ITER && a.bytes && threadIdx.x == 0) {
     const unsigned long long bq = (unsigned long long)tile.rows * n * sizeof(T);
-    const unsigned long long bv = 5ull * tile.rows * G * kact * sizeof(T);
+    const unsigned long long bv = 3ull * tile.rows * G * kact * sizeof(T);
     atomicAdd(a.bytes, bq + bv);
   }
 }
