@@ -55,6 +55,48 @@ double now_s() {
   return std::chrono::duration<double>(clk::now() - t0).count();
 }
 
+struct PassCfg {
+  int rowpass = 0, kv = 1, ks = 0, gr = 0, nim = 8;
+  size_t lds = 0;
+};
+
+// Pass configuration for element size sv over the whole batch: the
+// row-vector passes when every instance fits them, else the column-slot passes.
+PassCfg choose_cfg(const glm_shape* s, size_t sv, bool allow_rows) {
+  PassCfg c;
+  const int words = (int)(sv / 4);
+  int maxG = 0, maxni = 0;
+  bool k_div[5] = {true, true, true, true, true};   // K % 1, 2, 4 == 0
+  bool all16 = true;
+  int64_t off = 0;
+  for (int b = 0; b < s->batch; ++b) {
+    maxG = std::max(maxG, s->G[b]);
+    for (int i = 0; i < s->G[b]; ++i) maxni = std::max(maxni, s->n[off + i]);
+    off += s->G[b];
+    k_div[2] = k_div[2] && s->K[b] % 2 == 0;
+    k_div[4] = k_div[4] && s->K[b] % 4 == 0;
+    all16 = all16 && s->K[b] == 16;
+  }
+  c.nim = maxni <= 8 ? 8 : maxni <= 16 ? 16 : maxni <= 24 ? 24 : maxni <= 32 ? 32 : 64;
+  c.kv = 1;
+  for (int kv = (sv == 4) ? 4 : 2; kv > 1; kv /= 2)
+    if (k_div[kv] && c.nim * kv * words <= kProjSliceRegs) {
+      c.kv = kv;
+      break;
+    }
+  c.ks = (all16 && c.kv == ((sv == 4) ? 4 : 2)) ? 16 : 0;
+  // the Omega column in registers next to the projection slice, else in LDS
+  c.gr = (maxG <= 32 && (32 + c.nim * c.kv) * words <= kProjSliceRegs) ? 32 : 0;
+  bool fits = c.nim * words <= kProjSliceRegs;
+  if (c.gr == 0) fits = fits && (size_t)maxG * maxG * sv <= kRowOmegaLds;
+  for (int b = 0; b < s->batch; ++b) fits = fits && s->G[b] * s->K[b] / c.kv <= PROJ_NT;
+  c.rowpass = (fits && allow_rows) ? 1 : 0;
+  if (c.rowpass)
+    c.lds = ((size_t)PROJ_NT * (PROJ_NV * c.kv + PROJ_NQ) + PROJ_QPAD) * sv +
+            (c.gr == 0 ? (size_t)maxG * maxG * sv : 0);
+  return c;
+}
+
 struct Plan {
   int B = 0;
   glm_precision prec = GLM_FP64;
@@ -68,12 +110,14 @@ struct Plan {
           sumCK = 0, sumTp = 0, sumRc = 0;
   int nrhs = 0, ntiles = 0, nblk = 0, maxK = 0, maxn = 0, maxni = 0, maxkc = 0;
   int kc_t = 1, sl = 1;
-  int rowpass = 0, kv = 1, ks = 0, gr = 0, nim = 8;
-  size_t lds_inner = 0, lds64 = 0;
+  // projection-pass configuration per arithmetic precision (index 0 = FP32
+  // inner solves of the mixed path, 1 = FP64 solves); lds64 is the residual pass
+  PassCfg cfg[2];
+  size_t lds64 = 0;
   // byte offsets inside the workspace
   size_t o_Q64, o_Q32, o_R, o_Nb, o_colblk, o_inst, o_blk, o_tile, o_qrs, o_qrn, o_chunks,
       o_rinst, o_rinst_index, o_flags, o_active, o_icount, o_count, o_st, o_ost, o_alpha,
-      o_Om32, o_g, o_u, o_wf, o_yf, o_Tpart, o_Tm, o_dpart, o_cpart, o_gc, o_uc, o_wc,
+      o_Om32, o_g, o_u, o_wf, o_yf, o_y64, o_Tpart, o_Tm, o_dpart, o_cpart, o_gc, o_uc, o_wc,
       o_wc64, o_rho0, o_rhoc, o_lb, o_bytes;
   size_t total = 0;
 };
@@ -111,51 +155,23 @@ int validate(const glm_shape* s) {
   return GLM_OK;
 }
 
-int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow_rows = true) {
+// allow_rows[pi]: the row-vector passes may be used for precision index pi
+int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = true,
+              bool allow64 = true) {
   int rc = validate(s);
   if (rc != GLM_OK) return rc;
   p = Plan();
   p.B = s->batch;
   p.prec = prec;
-  const size_t sv = (prec == GLM_MIXED) ? sizeof(float) : sizeof(double);
   int64_t sum_rows = 0;
   for (int b = 0; b < p.B; ++b) sum_rows += s->M[b];
   int rc_rows = (int)std::max<int64_t>(kMinTileRows, (sum_rows + kTargetTiles - 1) / kTargetTiles);
-  // projection-pass flavour for the whole batch: the row-vector passes when
-  // every instance fits them, else the column-slot passes
-  {
-    const int words = (int)(sv / 4);
-    int maxG = 0, maxni = 0;
-    bool k_div[5] = {true, true, true, true, true};   // K % 1, 2, 4 == 0
-    bool all16 = true;
-    int64_t off = 0;
-    for (int b = 0; b < p.B; ++b) {
-      maxG = std::max(maxG, s->G[b]);
-      for (int i = 0; i < s->G[b]; ++i) maxni = std::max(maxni, s->n[off + i]);
-      off += s->G[b];
-      k_div[2] = k_div[2] && s->K[b] % 2 == 0;
-      k_div[4] = k_div[4] && s->K[b] % 4 == 0;
-      all16 = all16 && s->K[b] == 16;
-    }
-    p.nim = maxni <= 8 ? 8 : maxni <= 16 ? 16 : maxni <= 24 ? 24 : maxni <= 32 ? 32 : 64;
-    p.kv = 1;
-    for (int kv = (sv == 4) ? 4 : 2; kv > 1; kv /= 2)
-      if (k_div[kv] && p.nim * kv * words <= kProjSliceRegs) {
-        p.kv = kv;
-        break;
-      }
-    p.ks = (all16 && p.kv == ((sv == 4) ? 4 : 2)) ? 16 : 0;
-    // the Omega column in registers next to the projection slice, else in LDS
-    p.gr = (maxG <= 32 && (32 + p.nim * p.kv) * words <= kProjSliceRegs) ? 32 : 0;
-    bool fits = p.nim * words <= kProjSliceRegs;
-    if (p.gr == 0) fits = fits && (size_t)maxG * maxG * sv <= kRowOmegaLds;
-    for (int b = 0; b < p.B; ++b) fits = fits && s->G[b] * s->K[b] / p.kv <= PROJ_NT;
-    p.rowpass = (fits && allow_rows) ? 1 : 0;
-    if (p.rowpass)
-      p.lds_inner = ((size_t)PROJ_NT * (PROJ_NV * p.kv + PROJ_NQ) + PROJ_QPAD) * sv +
-                    (p.gr == 0 ? (size_t)maxG * maxG * sv : 0);
-  }
-  bool rows_fit_all = true;
+  // FP64 solves run in both modes (in the mixed path as the continuation of
+  // a refinement the FP32 inner solves no longer advance)
+  const bool need32 = prec == GLM_MIXED;
+  p.cfg[0] = choose_cfg(s, sizeof(float), allow32 && need32);
+  p.cfg[1] = choose_cfg(s, sizeof(double), allow64);
+  bool rows_fit[2] = {true, true};
   int64_t noff = 0;
   for (int b = 0; b < p.B; ++b) {
     InstDesc in{};
@@ -184,23 +200,33 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow_rows =
     const size_t per_row = 2 * (size_t)in.G * in.K;
     in.rs64 = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * 8)));
     p.lds64 = std::max(p.lds64, per_row * 8 * in.rs64);
-    if (p.rowpass) {
-      const int P = in.G * in.K;
-      in.rpar = PROJ_NT / (P / p.kv);
-      // rows per sub-tile: the three vector slabs of pass B and the Q rows
-      // must fit the stager's per-thread registers
-      const int rows_v = PROJ_NV * PROJ_NT * p.kv / (3 * P);
-      const int rows_q = PROJ_NQ * PROJ_NT / n;
-      int rs = std::min(std::min(rows_v, rows_q), in.rpar * kRowsPerLane);
-      // every row group needs a row per sub-tile; otherwise (wide Q rows,
-      // few equations) the column-slot passes stream Q better
-      if (rs < in.rpar) rows_fit_all = false;
-      rs = rs / in.rpar * in.rpar;   // whole rows per row group
-      in.rs = std::max(rs, 1);
-    } else {
-      in.rs = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * sv)));
-      in.rpar = 1;
-      p.lds_inner = std::max(p.lds_inner, per_row * sv * in.rs);
+    for (int pi = 1; pi >= 0; --pi) {
+      if (pi == 0 && !need32) {   // FP64 only: one configuration
+        in.rs_t[0] = in.rs_t[1];
+        in.rpar_t[0] = in.rpar_t[1];
+        continue;
+      }
+      const size_t svp = pi ? sizeof(double) : sizeof(float);
+      PassCfg& c = p.cfg[pi];
+      if (c.rowpass) {
+        const int P = in.G * in.K;
+        const int rpar = PROJ_NT / (P / c.kv);
+        // rows per sub-tile: the three vector slabs of pass B and the Q rows
+        // must fit the stager's per-thread registers
+        const int rows_v = PROJ_NV * PROJ_NT * c.kv / (3 * P);
+        const int rows_q = PROJ_NQ * PROJ_NT / n;
+        int rs = std::min(std::min(rows_v, rows_q), rpar * kRowsPerLane);
+        // every row group needs a row per sub-tile; otherwise (wide Q rows,
+        // few equations) the column-slot passes stream Q better
+        if (rs < rpar) rows_fit[pi] = false;
+        rs = rs / rpar * rpar;   // whole rows per row group
+        in.rs_t[pi] = std::max(rs, 1);
+        in.rpar_t[pi] = rpar;
+      } else {
+        in.rs_t[pi] = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * svp)));
+        in.rpar_t[pi] = 1;
+        c.lds = std::max(c.lds, per_row * svp * in.rs_t[pi]);
+      }
     }
     // blocks
     int col = 0;
@@ -228,10 +254,11 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow_rows =
     }
     noff += in.G;
     // tiles: rows per tile a multiple of both sub-tile heights
-    int step = std::max(in.rs, in.rs64);
+    int step = std::max(std::max(in.rs_t[0], in.rs_t[1]), in.rs64);
     int trows = std::max(step, (rc_rows + step - 1) / step * step);
     in.tile0 = (int)p.tile.size();
-    in.tp_stride = std::max<int64_t>((int64_t)in.rpar * n * in.K, (int64_t)in.G * in.G);
+    in.tp_stride = std::max<int64_t>(
+        (int64_t)std::max(in.rpar_t[0], in.rpar_t[1]) * n * in.K, (int64_t)in.G * in.G);
     int part = 0;
     for (int r0 = 0; r0 < in.M; r0 += trows) {
       TileDesc td{};
@@ -273,11 +300,10 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow_rows =
     p.maxn = std::max(p.maxn, n);
     p.inst.push_back(in);
   }
-  if (p.rowpass && !rows_fit_all) {
-    // some instance does not suit the row-vector passes: plan again with the
-    // column-slot passes
-    return make_plan(s, prec, p, false);
-  }
+  // an instance does not suit the row-vector passes of some precision: plan
+  // again with the column-slot passes for that precision
+  if ((p.cfg[0].rowpass && !rows_fit[0]) || (p.cfg[1].rowpass && !rows_fit[1]))
+    return make_plan(s, prec, p, allow32 && rows_fit[0], allow64 && rows_fit[1]);
   p.nblk = (int)p.blk.size();
   p.ntiles = (int)p.tile.size();
   for (size_t r = 0; r < p.qr_nb.size(); ++r) p.qr_nb[r].flag = p.nblk + (int)r;
@@ -313,10 +339,13 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow_rows =
   p.o_ost = take(4 * p.nrhs);
   p.o_alpha = take(8 * p.B);
   p.o_Om32 = take(prec == GLM_MIXED ? 4 * p.sumG2 : 0);
-  p.o_g = take(sv * p.sumMGK);
-  p.o_u = take(sv * p.sumMGK);
-  p.o_wf = take(prec == GLM_MIXED ? 4 * p.sumMGK : 0);
-  p.o_yf = take(prec == GLM_MIXED ? 4 * p.sumMGK : 0);
+  // iteration vectors hold FP64 values in both modes (FP32 inner solves use
+  // the first half of each)
+  p.o_g = take(8 * p.sumMGK);
+  p.o_u = take(8 * p.sumMGK);
+  p.o_wf = take(prec == GLM_MIXED ? 8 * p.sumMGK : 0);   // inner correction (FP32 or FP64)
+  p.o_yf = take(prec == GLM_MIXED ? 4 * p.sumMGK : 0);   // refinement residual, FP32 copy
+  p.o_y64 = take(prec == GLM_MIXED ? 8 * p.sumMGK : 0);  // refinement residual, FP64
   p.o_Tpart = take(8 * p.sumTp);
   p.o_Tm = take(8 * p.sumTK);
   p.o_dpart = take(8 * (size_t)p.ntiles * KMAX);
@@ -412,12 +441,13 @@ PassLaunch<T> pass_args(glm_factor* f, const T* Q, const T* Om, const T* y, T* w
   a.w_nonzero = 0;
   a.kc_t = p.kc_t;
   a.sl = p.sl;
-  a.lds = (sizeof(T) == 8 && p.prec == GLM_MIXED) ? p.lds64 : p.lds_inner;
-  a.rowpass = p.rowpass;
-  a.kv = p.kv;
-  a.ks = p.ks;
-  a.gr = p.gr;
-  a.nim = p.nim;
+  const PassCfg& c = p.cfg[sizeof(T) == 8];
+  a.lds = c.lds;
+  a.rowpass = c.rowpass;
+  a.kv = c.kv;
+  a.ks = c.ks;
+  a.gr = c.gr;
+  a.nim = c.nim;
   return a;
 }
 
@@ -471,7 +501,8 @@ int project_rhs(glm_factor* f, const T* Q, const T* Om, const T* y, T* w, bool w
   if (int rc = run_pass_a<T>(f, a, PASS_A_RHS, s)) return rc;
   GLM_CHECK(launch_reduce_t<T>(f->d_inst(), f->d_tile(), f->d_active(),
                                f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
-                               f->at<T>(p.o_Tpart), f->at<T>(p.o_Tm), p.rowpass, s));
+                               f->at<T>(p.o_Tpart), f->at<T>(p.o_Tm),
+                               p.cfg[sizeof(T) == 8].rowpass, s));
   GLM_CHECK(launch_scalar_a<T>(f->d_inst(), f->d_tile(), f->d_active(), f->d_st(),
                                f->at<double>(p.o_dpart), f->at<T>(p.o_Tm),
                                f->at<double>(p.o_Nb), rvec, p.B, 0, 0, s));
@@ -542,7 +573,8 @@ int core_solve(glm_factor* f, const T* Q, const T* Om, const T* y, const double*
     if (int rc = run_pass_a<T>(f, aa, PASS_A_ITER, s)) return rc;
     GLM_CHECK(launch_reduce_t<T>(f->d_inst(), f->d_tile(), f->d_active(),
                                  f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
-                                 f->at<T>(p.o_Tpart), Tm, p.rowpass, s));
+                                 f->at<T>(p.o_Tpart), Tm,
+                                 p.cfg[sizeof(T) == 8].rowpass, s));
     GLM_CHECK(launch_scalar_a<T>(f->d_inst(), f->d_tile(), f->d_active(), f->d_st(),
                                  f->at<double>(p.o_dpart), Tm, f->at<double>(p.o_Nb),
                                  nullptr, p.B, 1, 1, s));
@@ -640,13 +672,12 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
     GLM_CHECK(launch_fill<double>(wc64, std::max<int64_t>(p.sumCK, 0), 0.0, s));
     f->launches += 2;
     float* yf = f->at<float>(p.o_yf);
-    float* wf = f->at<float>(p.o_wf);
     int step = 0;
     for (step = 0; step <= kMaxOuter; ++step) {
       // double-precision residual of the augmented system
       GLM_CHECK(launch_residual(f->d_inst(), f->d_tile(), p.ntiles, f->d_blk(),
                                 f->at<int>(p.o_colblk), f->d_active(), f->X, Om, y, u_out,
-                                beta_out, yf, f->at<double>(p.o_Tpart),
+                                beta_out, yf, f->at<double>(p.o_y64), f->at<double>(p.o_Tpart),
                                 f->at<double>(p.o_cpart), f->at<double>(p.o_dpart), p.kc_t,
                                 p.sl, p.lds64, s));
       GLM_CHECK(launch_reduce_t<double>(f->d_inst(), f->d_tile(), f->d_active(),
@@ -673,19 +704,48 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
                      h0.total_iters);
       }
       if (*f->h_count == 0) break;
-      int rc = core_solve<float>(f, f->at<float>(p.o_Q32), f->at<float>(p.o_Om32), yf,
-                                 f->at<double>(p.o_rho0),
-                                 p.sumCK ? f->at<double>(p.o_rhoc) : nullptr, wf, beta_out,
-                                 true, kInnerTol, kStallInner,
-                                 (max_iter > 0 && max_iter < kInnerMaxit) ? max_iter
-                                                                          : kInnerMaxit,
-                                 s);
-      if (rc) return rc;
-      GLM_CHECK(launch_update_u(f->d_inst(), f->d_tile(), p.ntiles, f->d_active(), f->d_st(),
-                                wf, u_out, s));
-      if (p.sumCK)
-        GLM_CHECK(launch_update_c(f->d_inst(), p.B, f->d_st(), f->at<double>(p.o_wc), wc64, s));
-      f->launches += 2;
+      // inner solves: FP32 for the rhs it still advances, FP64 for the others
+      for (int want = 0; want < 2; ++want) {
+        GLM_CHECK(launch_select_inner(f->d_inst(), p.B, f->d_st(), f->at<int>(p.o_ost),
+                                      f->d_active(), want, s));
+        GLM_CHECK(launch_count(f->d_active(), p.B, f->at<int>(p.o_count), s));
+        GLM_CHECK(hipMemcpyAsync(f->h_count, f->at<int>(p.o_count), sizeof(int),
+                                 hipMemcpyDeviceToHost, s));
+        GLM_CHECK(hipStreamSynchronize(s));
+        f->launches += 2;
+        if (*f->h_count == 0) continue;
+        const double* rhoc = p.sumCK ? f->at<double>(p.o_rhoc) : nullptr;
+        if (want == 0) {
+          float* wf = f->at<float>(p.o_wf);
+          int rc = core_solve<float>(f, f->at<float>(p.o_Q32), f->at<float>(p.o_Om32), yf,
+                                     f->at<double>(p.o_rho0), rhoc, wf, beta_out, true,
+                                     kInnerTol, kStallInner,
+                                     (max_iter > 0 && max_iter < kInnerMaxit) ? max_iter
+                                                                              : kInnerMaxit,
+                                     s);
+          if (rc) return rc;
+          GLM_CHECK(launch_update_u<float>(f->d_inst(), f->d_tile(), p.ntiles, f->d_active(),
+                                           f->d_st(), wf, u_out, s));
+        } else {
+          if (log_on())
+            std::fprintf(stderr, "[glm %.3fs] refinement step %d: %d instances continue in FP64\n",
+                         now_s(), step, *f->h_count);
+          double* w64 = f->at<double>(p.o_wf);
+          int rc = core_solve<double>(f, f->at<double>(p.o_Q64), Om, f->at<double>(p.o_y64),
+                                      f->at<double>(p.o_rho0), rhoc, w64, beta_out, true,
+                                      kInnerTol, kStallFP64, max_iter, s);
+          if (rc) return rc;
+          GLM_CHECK(launch_update_u<double>(f->d_inst(), f->d_tile(), p.ntiles, f->d_active(),
+                                            f->d_st(), w64, u_out, s));
+        }
+        if (p.sumCK)
+          GLM_CHECK(launch_update_c(f->d_inst(), p.B, f->d_st(), f->at<double>(p.o_wc), wc64, s));
+        f->launches += 2;
+      }
+      // the next refinement residual covers every rhs still refining
+      GLM_CHECK(launch_select_inner(f->d_inst(), p.B, f->d_st(), f->at<int>(p.o_ost),
+                                    f->d_active(), -1, s));
+      ++f->launches;
     }
     f->stats.outer_steps = step;
     if (uc_out && p.sumCK)

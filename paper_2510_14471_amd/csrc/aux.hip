@@ -70,6 +70,8 @@ __global__ void k_state_init(const InstDesc* __restrict__ insts, int B,
     s.rnorm2 = s.ynorm2 = 0.0;
     s.status = bad ? ST_RANK : ST_ACTIVE;
     s.iters = s.since = s.total_iters = 0;
+    s.itol = 0.0;
+    s.esc = s.pad = 0;
     st[in.rhs0 + threadIdx.x] = s;
     if (ost) ost[in.rhs0 + threadIdx.x] = bad ? ST_RANK : ST_ACTIVE;
   }
@@ -119,6 +121,7 @@ struct ResArgs {
   const double* __restrict__ w;
   const double* __restrict__ beta;
   float* rho;
+  double* rho64;   // FP64 copy of rho_y (refinement continued in FP64), may be null
   double* Tpart;
   double* rpart;   // [tile][KMAX]  ||rho_y||^2
   double* ypart;   // [tile][KMAX]  ||y||^2
@@ -211,6 +214,7 @@ __global__ void __launch_bounds__(NT) k_residual(ResArgs a) {
           const double yv = a.y ? a.y[e0 + k] : 0.0;
           const double r = yv - Bs[l0 + k] - xb[k];
           a.rho[e0 + k] = (float)r;
+          if (a.rho64) a.rho64[e0 + k] = r;
           racc[k] += r * r;
           yacc[k] += yv * yv;
         }
@@ -325,12 +329,22 @@ k_outer_check(const InstDesc* __restrict__ insts, int* __restrict__ inst_active,
       const double prev = s.rnorm2;   // residual of the previous refinement step
       s.rnorm2 = R2;
       s.ynorm2 = Y2;
+      // A healthy FP32 inner solve cuts the residual by about its tolerance;
+      // one that gains less than a factor 10 in norm no longer resolves the
+      // remaining error (FP32 rounding of Q and Omega), and the refinement
+      // continues with FP64 inner solves.  Once those stop halving the norm,
+      // refinement has reached what the arithmetic allows.
+      const bool weak = step > 0 && !(R2 < 1e-2 * prev);
+      const bool stalled = step > 0 && !(R2 < 0.25 * prev);
       if (!(R2 > tol * tol * Y2)) {
         ost[s_idx] = ST_CONVERGED;
         s.status = ST_IDLE;
-      } else if (step > 0 && !(R2 < 0.25 * prev)) {
-        // the residual no longer halves: refinement has reached the accuracy
-        // the arithmetic allows (the last correction is kept)
+      } else if (!s.esc && weak && !last_step && isfinite(R2)) {
+        s.esc = 1;
+        s.status = ST_ACTIVE;
+        s_any = 1;
+      } else if (stalled) {
+        // the last correction is kept
         ost[s_idx] = ST_STAGNATED;
         s.status = ST_IDLE;
       } else if (last_step || !isfinite(R2)) {
@@ -340,6 +354,9 @@ k_outer_check(const InstDesc* __restrict__ insts, int* __restrict__ inst_active,
         s.status = ST_ACTIVE;
         s_any = 1;
       }
+      // an FP64 continuation solve aims a little below the outer target
+      if (s.status == ST_ACTIVE && s.esc)
+        s.itol = fmin(1e-3, fmax(1e-15, 0.1 * tol * sqrt(Y2 / R2)));
     }
     __syncthreads();
   }
@@ -351,11 +368,12 @@ k_outer_check(const InstDesc* __restrict__ insts, int* __restrict__ inst_active,
   }
 }
 
-// u += du (single -> double) for the rhs of the inner solve, over one tile.
+// u += du for the rhs of the inner solve (FP32 or FP64 correction), over one tile.
+template <typename T>
 __global__ void __launch_bounds__(NT)
 k_update_u(const InstDesc* __restrict__ insts, const TileDesc* __restrict__ tiles,
            const int* __restrict__ inst_active, const RhsState* __restrict__ st,
-           const float* __restrict__ du, double* __restrict__ u) {
+           const T* __restrict__ du, double* __restrict__ u) {
   const TileDesc tile = tiles[blockIdx.x];
   if (!inst_active[tile.inst]) return;
   const InstDesc in = insts[tile.inst];
@@ -512,10 +530,11 @@ template hipError_t launch_copy_tc<float>(const InstDesc*, int, const float*, do
 hipError_t launch_residual(const InstDesc* insts, const TileDesc* tiles, int ntiles,
                            const BlockDesc* blks, const int* colblk, const int* inst_active,
                            const double* X, const double* Om, const double* y,
-                           const double* w, const double* beta, float* rho, double* Tpart,
-                           double* rpart, double* ypart, int kc_t, int sl, size_t lds,
-                           hipStream_t s) {
-  ResArgs a{insts, tiles, blks, colblk, inst_active, X, Om, y, w, beta, rho, Tpart, rpart, ypart};
+                           const double* w, const double* beta, float* rho, double* rho64,
+                           double* Tpart, double* rpart, double* ypart, int kc_t, int sl,
+                           size_t lds, hipStream_t s) {
+  ResArgs a{insts, tiles, blks, colblk, inst_active, X, Om, y, w, beta, rho, rho64, Tpart,
+            rpart, ypart};
   GLM_LAUNCH_RES(1, 1) GLM_LAUNCH_RES(1, 2) GLM_LAUNCH_RES(1, 3) GLM_LAUNCH_RES(1, 4)
   GLM_LAUNCH_RES(1, 8) GLM_LAUNCH_RES(2, 1) GLM_LAUNCH_RES(2, 2) GLM_LAUNCH_RES(2, 3)
   GLM_LAUNCH_RES(2, 4) GLM_LAUNCH_RES(2, 8) GLM_LAUNCH_RES(4, 1) GLM_LAUNCH_RES(4, 2)
@@ -537,11 +556,43 @@ hipError_t launch_outer_check(const InstDesc* insts, int B, int* inst_active, Rh
   return hipGetLastError();
 }
 
+template <typename T>
 hipError_t launch_update_u(const InstDesc* insts, const TileDesc* tiles, int ntiles,
-                           const int* inst_active, const RhsState* st, const float* du,
+                           const int* inst_active, const RhsState* st, const T* du,
                            double* u, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_u, dim3(ntiles), dim3(NT), 0, s, insts, tiles, inst_active, st,
-                     du, u);
+  hipLaunchKernelGGL(k_update_u<T>, dim3(ntiles), dim3(NT), 0, s, insts, tiles, inst_active,
+                     st, du, u);
+  return hipGetLastError();
+}
+template hipError_t launch_update_u<float>(const InstDesc*, const TileDesc*, int, const int*,
+                                           const RhsState*, const float*, double*, hipStream_t);
+template hipError_t launch_update_u<double>(const InstDesc*, const TileDesc*, int, const int*,
+                                            const RhsState*, const double*, double*,
+                                            hipStream_t);
+
+// Mixed path: the rhs whose refinement continues take part in the next inner
+// solve of precision `want` (0 = FP32, 1 = FP64; -1 = all of them, which only
+// sets the instance activity for the refinement residual).
+__global__ void k_select_inner(const InstDesc* __restrict__ insts, int B,
+                               RhsState* __restrict__ st, const int* __restrict__ ost,
+                               int* __restrict__ inst_active, int want) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const InstDesc in = insts[b];
+  int any = 0;
+  for (int k = 0; k < in.K; ++k) {
+    RhsState& s = st[in.rhs0 + k];
+    const bool on = ost[in.rhs0 + k] == ST_ACTIVE && (want < 0 || s.esc == want);
+    if (want >= 0 && s.status != ST_RANK) s.status = on ? ST_ACTIVE : ST_IDLE;
+    any |= on;
+  }
+  inst_active[b] = any;
+}
+
+hipError_t launch_select_inner(const InstDesc* insts, int B, RhsState* st, const int* ost,
+                               int* inst_active, int want, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_inner, dim3((B + 63) / 64), dim3(64), 0, s, insts, B, st, ost,
+                     inst_active, want);
   return hipGetLastError();
 }
 

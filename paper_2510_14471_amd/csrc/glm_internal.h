@@ -27,10 +27,10 @@ struct InstDesc {
   int rhs0;        // first (instance, rhs) state index
   int tile0;       // first tile of this instance
   int ntiles;
-  int rs;          // rows per LDS-staged sub-tile
+  int rs_t[2];     // rows per LDS-staged sub-tile of the passes (FP32, FP64)
+  int rpar_t[2];   // row groups per workgroup of the passes (FP32, FP64)
   int maxit;       // PCG iteration bound m - n + 1
   int rs64;        // rows per sub-tile for the double-precision residual pass
-  int rpar;        // row groups per workgroup of the row-vector passes
   int nimax;       // largest n_i of the instance
   int64_t tp_stride;  // elements per tile partial: max(rpar n K, G G)
   int64_t q_off;   // Q / X (M x n)
@@ -64,8 +64,21 @@ struct QRJob {
 struct RhsState {
   double c, c1, d, lam, mu, cmin;
   double rnorm2, ynorm2;       // refinement residual and reference norms (mixed)
+  double itol;                 // inner tolerance of an FP64 refinement solve (0: default)
   int status, iters, since, total_iters;
+  int esc;                     // mixed path: inner solves continue in FP64
+  int pad;
 };
+
+// Pass geometry of precision T (index 0 = FP32, 1 = FP64).
+template <typename T>
+__host__ __device__ inline int rows_of(const InstDesc& in) {
+  return in.rs_t[sizeof(T) == 8];
+}
+template <typename T>
+__host__ __device__ inline int rpar_of(const InstDesc& in) {
+  return in.rpar_t[sizeof(T) == 8];
+}
 
 struct RedChunk {
   int inst, p0;
@@ -161,18 +174,21 @@ hipError_t launch_copy_tc(const InstDesc* insts, int B, const T* Tm, double* wc,
 hipError_t launch_residual(const InstDesc* insts, const TileDesc* tiles, int ntiles,
                            const BlockDesc* blks, const int* colblk, const int* inst_active,
                            const double* X, const double* Om, const double* y,
-                           const double* w, const double* beta, float* rho, double* Tpart,
-                           double* rpart, double* ypart, int kc_t, int sl, size_t lds,
-                           hipStream_t s);
+                           const double* w, const double* beta, float* rho, double* rho64,
+                           double* Tpart, double* rpart, double* ypart, int kc_t, int sl,
+                           size_t lds, hipStream_t s);
 hipError_t launch_outer_check(const InstDesc* insts, int B, int* inst_active, RhsState* st,
                               int* ost, const double* rpart, const double* ypart,
                               const double* XtW, const double* h2, const double* Rc,
                               const double* rvec, const double* beta, const double* wc,
                               double* rho0, double* rhoc, double tol, int step,
                               int last_step, hipStream_t s);
+template <typename T>
 hipError_t launch_update_u(const InstDesc* insts, const TileDesc* tiles, int ntiles,
-                           const int* inst_active, const RhsState* st, const float* du,
+                           const int* inst_active, const RhsState* st, const T* du,
                            double* u, hipStream_t s);
+hipError_t launch_select_inner(const InstDesc* insts, int B, RhsState* st, const int* ost,
+                               int* inst_active, int want, hipStream_t s);
 hipError_t launch_update_c(const InstDesc* insts, int B, const RhsState* st,
                            const double* dwc, double* wc64, hipStream_t s);
 hipError_t launch_grad(const InstDesc* insts, const TileDesc* tiles, int ntiles, int B,

@@ -157,7 +157,7 @@ k_pass_a(VecArgs<T> a) {
   const TileDesc tile = a.tiles[blockIdx.x];
   if (!a.inst_active[tile.inst]) return;
   const InstDesc in = a.insts[tile.inst];
-  const int G = in.G, K = in.K, n = in.n, rs = in.rs;
+  const int G = in.G, K = in.K, n = in.n, rs = rows_of<T>(in);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Us = reinterpret_cast<T*>(smem_raw);
   T* Bs = Us + (size_t)rs * G * K;
@@ -261,7 +261,7 @@ k_pass_b(VecArgs<T> a) {
   const TileDesc tile = a.tiles[blockIdx.x];
   if (!a.inst_active[tile.inst]) return;
   const InstDesc in = a.insts[tile.inst];
-  const int G = in.G, K = in.K, n = in.n, rs = in.rs;
+  const int G = in.G, K = in.K, n = in.n, rs = rows_of<T>(in);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Us = reinterpret_cast<T*>(smem_raw);
   T* Bs = Us + (size_t)rs * G * K;
@@ -370,7 +370,7 @@ k_reduce_t(const InstDesc* __restrict__ insts, const TileDesc* __restrict__ tile
   const int pr = ch.p0 + threadIdx.x;
   if (pr >= nk) return;
   const int64_t base = tiles[in.tile0].tp_off;
-  const int slots = use_rpar ? in.rpar : 1;   // row-group partials inside a tile
+  const int slots = use_rpar ? rpar_of<T>(in) : 1;   // row-group partials inside a tile
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   const int64_t st4 = in.tp_stride;
   for (int r = 0; r < slots; ++r) {
@@ -502,7 +502,7 @@ __global__ void k_scalar_b(const InstDesc* __restrict__ insts, int* __restrict__
         s.total_iters += 1;
         if (!isfinite(cn)) {
           s.status = ST_BREAKDOWN;
-        } else if (sqrt(cn / s.c1) <= tol) {
+        } else if (sqrt(cn / s.c1) <= (s.itol > 0.0 ? s.itol : tol)) {
           s.status = ST_CONVERGED;
         } else {
           // progress = c at least halves relative to the reference value;
@@ -745,6 +745,9 @@ template hipError_t launch_scalar_a<float>(const InstDesc*, const TileDesc*, con
                                            RhsState*, const double*, float*, const double*,
                                            const double*, int, int, int, hipStream_t);
 template hipError_t launch_trisolve<double, double, true, false>(
+    const InstDesc*, const BlockDesc*, int, const int*, const RhsState*, int, const double*,
+    const double*, int, double*, int, hipStream_t);
+template hipError_t launch_trisolve<double, double, true, true>(
     const InstDesc*, const BlockDesc*, int, const int*, const RhsState*, int, const double*,
     const double*, int, double*, int, hipStream_t);
 template hipError_t launch_trisolve<float, double, true, true>(

@@ -240,9 +240,9 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
   const TileDesc tile = a.tiles[blockIdx.x];
   if (!a.inst_active[tile.inst]) return;
   const InstDesc in = a.insts[tile.inst];
-  const int G = in.G, K = KS ? KS : in.K, n = in.n, rs = in.rs, P = G * K, KQ = K / KV;
+  const int G = in.G, K = KS ? KS : in.K, n = in.n, rs = rows_of<T>(in), P = G * K, KQ = K / KV;
   const int PP = G * KQ;           // lanes per row
-  const int rpar = in.rpar, nimax = in.nimax;
+  const int rpar = rpar_of<T>(in), nimax = in.nimax;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   T* Oms = lds + (size_t)PNT * (NV * KV + NQ) + PROJ_QPAD;   // Omega unless in registers
@@ -421,9 +421,9 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
   const TileDesc tile = a.tiles[blockIdx.x];
   if (!a.inst_active[tile.inst]) return;
   const InstDesc in = a.insts[tile.inst];
-  const int G = in.G, K = KS ? KS : in.K, n = in.n, rs = in.rs, P = G * K, KQ = K / KV;
+  const int G = in.G, K = KS ? KS : in.K, n = in.n, rs = rows_of<T>(in), P = G * K, KQ = K / KV;
   const int PP = G * KQ;
-  const int rpar = in.rpar, nimax = in.nimax;
+  const int rpar = rpar_of<T>(in), nimax = in.nimax;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   T* Oms = lds + (size_t)PNT * (NV * KV + NQ) + PROJ_QPAD;

@@ -96,11 +96,7 @@ def test_large_single_sur(glmlib, precision):
 
 # -- singular Omega of rank G - 2 with 10 cross-equation restrictions -----------------
 
-@pytest.mark.parametrize("precision", [
-    "fp64",
-    pytest.param("mixed", marks=pytest.mark.skip(
-        reason="the FP32 inner solves stall near 3e-5 on this workload and the "
-               "refinement stops there; FP64 continuation of the refinement pending"))])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_singular_restricted_workload(glmlib, precision):
     inst = list(synth.config4())[0]
     out = solve(glmlib, [inst], precision)
