@@ -85,6 +85,16 @@ PassCfg choose_cfg(const glm_shape* s, size_t sv, bool allow_rows) {
       break;
     }
   c.ks = (all16 && c.kv == ((sv == 4) ? 4 : 2)) ? 16 : 0;
+  // FP32 with sixteen rhs everywhere: the Omega apply runs on the matrix cores
+  // (gr < 0 encodes the largest padded G, -16 / -32 / -64)
+  if (sv == 4 && all16 && maxG <= 64 && c.nim <= 32 && allow_rows) {
+    c.kv = 4;
+    c.ks = 16;
+    c.gr = maxG <= 16 ? -16 : maxG <= 32 ? -32 : -64;
+    c.rowpass = 1;
+    c.lds = ((size_t)PROJ_NT * (PROJ_NV * c.kv + PROJ_NQ) + PROJ_QPAD) * sv;
+    return c;
+  }
   // the Omega column in registers next to the projection slice, else in LDS
   c.gr = (maxG <= 32 && (32 + c.nim * c.kv) * words <= kProjSliceRegs) ? 32 : 0;
   bool fits = c.nim * words <= kProjSliceRegs;
@@ -210,7 +220,9 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
       PassCfg& c = p.cfg[pi];
       if (c.rowpass) {
         const int P = in.G * in.K;
-        const int rpar = PROJ_NT / (P / c.kv);
+        // matrix-core passes: 64 / Gp row slots (Gp = G padded to a power of two >= 4)
+        const int gp = in.G <= 4 ? 4 : in.G <= 8 ? 8 : in.G <= 16 ? 16 : in.G <= 32 ? 32 : 64;
+        const int rpar = c.gr < 0 ? 64 / gp : PROJ_NT / (P / c.kv);
         // rows per sub-tile: the three vector slabs of pass B and the Q rows
         // must fit the stager's per-thread registers
         const int rows_v = PROJ_NV * PROJ_NT * c.kv / (3 * P);

@@ -169,9 +169,10 @@ struct Stage3 {
 };
 
 // out[k] = sum over lanes of acc[v] for the lanes holding right-hand side k.
-// The reduction buffer aliases the staging area, so every wave must be done
-// reading the last sub-tile first.
-template <int KV>
+// Lane -> rhs group: lane % KQ in the vector-ALU mapping, (lane % 64) / 16 in
+// the matrix-core mapping (MF).  The reduction buffer aliases the staging
+// area, so every wave must be done reading the last sub-tile first.
+template <int KV, bool MF>
 __device__ void reduce_k(const double (&acc)[KV], bool on, int K, int KQ, double* red,
                          double* out) {
   __syncthreads();
@@ -181,7 +182,12 @@ __device__ void reduce_k(const double (&acc)[KV], bool on, int K, int KQ, double
   if ((int)threadIdx.x < K) {
     const int k = threadIdx.x, kq = k / KV, v = k - kq * KV;
     double s = 0.0;
-    for (int l = kq; l < PNT; l += KQ) s += red[l * KV + v];
+    if (MF) {
+      for (int w = 0; w < PNT / 64; ++w)
+        for (int l = 0; l < 16; ++l) s += red[(w * 64 + kq * 16 + l) * KV + v];
+    } else {
+      for (int l = kq; l < PNT; l += KQ) s += red[l * KV + v];
+    }
     out[k] = s;
   }
   __syncthreads();
@@ -235,6 +241,87 @@ __device__ __forceinline__ void zero_lds(T* lds, int count) {
   for (int e = threadIdx.x; e < count; e += PNT) lds[e] = T(0);
 }
 
+// ---- Omega apply on the matrix cores (FP32, sixteen right-hand sides) ------
+//
+// B[t][i][k] = sum_j U[t][j][k] Omega[j][i] for one block of rows is the
+// product of a (k x j) slice of U and a (j x i) block of Omega, done with
+// v_mfma_f32_16x16x4f32: M = 16 right-hand sides, N = 16 output columns,
+// 4 values of j per instruction.  The result lands as lane l, register r ->
+// (column l % 16, rhs 4 (l / 16) + r), so each lane holds the four
+// consecutive rhs k0 = 4 (l / 16) .. k0 + 3 of one output column, which is the
+// lane layout the rest of the pass uses.
+//   Gp = G rounded up to a power of two (at least 4).
+//   Gp <= 16: the 16 columns are (row tq, equation i) pairs, tq < 16 / Gp, so
+//     one product covers 16 / Gp rows; the K dimension runs over (row, j)
+//     pairs and Omega enters block-diagonally (zero across rows).
+//   Gp = 32, 64: the columns are 16 equations of one block; waves split the
+//     Gp / 16 blocks, and the K dimension runs over j.
+// Entries of Omega beyond G are zero, so the U values they meet (the next
+// equation's or row's, or zeroed LDS) do not contribute.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+struct MfMap {
+  int Gp, small, RB, WPB, rgrp, tq, i, kq, n16;
+};
+
+__device__ __forceinline__ MfMap mf_map(int G) {
+  MfMap m;
+  m.Gp = G <= 4 ? 4 : G <= 8 ? 8 : G <= 16 ? 16 : G <= 32 ? 32 : 64;
+  m.small = m.Gp <= 16;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  m.n16 = l & 15;
+  m.kq = l >> 4;
+  m.RB = m.small ? 16 / m.Gp : 1;
+  m.WPB = m.small ? 4 : 64 / m.Gp;
+  m.rgrp = m.small ? w : w % m.WPB;
+  m.tq = m.small ? m.n16 / m.Gp : 0;
+  m.i = m.small ? m.n16 % m.Gp : (w / m.WPB) * 16 + m.n16;
+  return m;
+}
+
+// B-operand registers: Omega entries this lane feeds to each product.
+template <int NB>
+__device__ __forceinline__ void mf_load_omega(const MfMap& m, int G, const float* __restrict__ Om,
+                                              float (&bom)[NB]) {
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    float v = 0.f;
+    if (m.small) {
+      if (q < 4) {
+        const int kk = 4 * q + m.kq, tr = kk / m.Gp, j = kk - tr * m.Gp;
+        if (tr == m.tq && j < G && m.i < G) v = Om[j * G + m.i];
+      }
+    } else if (q < m.Gp / 4) {
+      const int j = 4 * q + m.kq;
+      if (j < G && m.i < G) v = Om[j * G + m.i];
+    }
+    bom[q] = v;
+  }
+}
+
+// acc[r] = B[t0 + tq][i][4 kq + r] for the row block starting at t0 (P = 16 G).
+template <int NB>
+__device__ __forceinline__ mf4 mf_apply(const MfMap& m, const float* __restrict__ Us, int t0,
+                                        int P, const float (&bom)[NB]) {
+  mf4 acc = {0.f, 0.f, 0.f, 0.f};
+  if (m.small) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kk = 4 * q + m.kq, tr = kk / m.Gp, j = kk - tr * m.Gp;
+      const float a = Us[(t0 + tr) * P + j * 16 + m.n16];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bom[q], acc, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      if (q < m.Gp / 4) {
+        const float a = Us[t0 * P + (4 * q + m.kq) * 16 + m.n16];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bom[q], acc, 0, 0, 0);
+      }
+  }
+  return acc;
+}
+
 template <typename T, int KV, int KS, int GR, int NIM, int MODE>
 __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
   const TileDesc tile = a.tiles[blockIdx.x];
@@ -259,11 +346,25 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
   const T* __restrict__ Om = a.Om + in.om_off;
   if (GR == 0)
     for (int e = threadIdx.x; e < G * G; e += PNT) Oms[e] = Om[e];
+  constexpr bool MF = GR < 0;                // Omega apply on the matrix cores
+  constexpr int NB = MF ? -GR / 4 : 1;
   const int lane = threadIdx.x;
-  const bool on = lane < rpar * PP;
-  const int r = on ? lane / PP : 0;
-  const int pr = on ? lane - r * PP : 0;
-  const int i = pr / KQ, kq = pr - (pr / KQ) * KQ;
+  bool on;
+  int r, i, kq;
+  MfMap mm{};
+  if constexpr (MF) {
+    mm = mf_map(G);
+    on = mm.i < G;
+    r = mm.rgrp * mm.RB + mm.tq;
+    i = on ? mm.i : 0;
+    kq = mm.kq;
+  } else {
+    on = lane < rpar * PP;
+    r = on ? lane / PP : 0;
+    const int pr = on ? lane - r * PP : 0;
+    i = pr / KQ;
+    kq = pr - (pr / KQ) * KQ;
+  }
   const int k0 = kq * KV;
   const BlockDesc bd = a.blks[in.blk0 + i];
   const int ni = bd.ni, col = bd.col;
@@ -272,6 +373,8 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
 #pragma unroll
     for (int j = 0; j < GR; ++j) om[j] = (j < G) ? Om[j * G + i] : T(0);
   }
+  float bom[NB];
+  if constexpr (MF) mf_load_omega<NB>(mm, G, Om, bom);
   T tacc[NIM][KV];
 #pragma unroll
   for (int c = 0; c < NIM; ++c)
@@ -353,13 +456,25 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
       }
       __syncthreads();
     }
-    if (on) {
-      for (int t = r; t < nr; t += rpar) {
+    // rows t = r + it * rpar; the trip count is uniform across the workgroup
+    for (int it = 0; it * rpar < nr; ++it) {
+      const int t = r + it * rpar;
+      {
         T b[KV];
 #pragma unroll
         for (int v = 0; v < KV; ++v) b[v] = T(0);
+        if constexpr (MF) {
+          if (have_w) {
+            const mf4 acc = mf_apply<NB>(mm, Us, t - mm.tq, P, bom);
+#pragma unroll
+            for (int v = 0; v < KV; ++v) b[v] = acc[v];
+          }
+        }
+        if (!(on && t < nr)) continue;
         const T* urow = Us + (size_t)t * P + k0;
-        if (have_w) apply_omega<T, KV, KS, GR>(urow, K, G, i, om, Oms, b);
+        if constexpr (!MF) {
+          if (have_w) apply_omega<T, KV, KS, GR>(urow, K, G, i, om, Oms, b);
+        }
         if (MODE == PASS_A_ITER) {
           const Vec<T, KV> ui = vload<T, KV>(urow + i * K);
 #pragma unroll
@@ -402,7 +517,7 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
       }
   }
   if (MODE == PASS_A_ITER) {
-    reduce_k<KV>(dacc, on, K, KQ, reinterpret_cast<double*>(smem_raw), dsum);
+    reduce_k<KV, MF>(dacc, on, K, KQ, reinterpret_cast<double*>(smem_raw), dsum);
     if ((int)threadIdx.x < K) a.dpart[(int64_t)blockIdx.x * KMAX + threadIdx.x] = dsum[threadIdx.x];
   }
   // Algorithmic bytes of one iteration: Q twice (once per pass) and each of
@@ -441,11 +556,25 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
   const T* __restrict__ Om = a.Om + in.om_off;
   if (GR == 0 && MODE != PASS_B_EXPAND)
     for (int e = threadIdx.x; e < G * G; e += PNT) Oms[e] = Om[e];
+  constexpr bool MF = GR < 0;                // Omega apply on the matrix cores
+  constexpr int NB = MF ? -GR / 4 : 1;
   const int lane = threadIdx.x;
-  const bool on = lane < rpar * PP;
-  const int r = on ? lane / PP : 0;
-  const int pr = on ? lane - r * PP : 0;
-  const int i = pr / KQ, kq = pr - (pr / KQ) * KQ;
+  bool on;
+  int r, i, kq;
+  MfMap mm{};
+  if constexpr (MF) {
+    mm = mf_map(G);
+    on = mm.i < G;
+    r = mm.rgrp * mm.RB + mm.tq;
+    i = on ? mm.i : 0;
+    kq = mm.kq;
+  } else {
+    on = lane < rpar * PP;
+    r = on ? lane / PP : 0;
+    const int pr = on ? lane - r * PP : 0;
+    i = pr / KQ;
+    kq = pr - (pr / KQ) * KQ;
+  }
   const int k0 = kq * KV;
   const BlockDesc bd = a.blks[in.blk0 + i];
   const int ni = bd.ni, col = bd.col;
@@ -454,6 +583,9 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
 #pragma unroll
     for (int j = 0; j < GR; ++j) om[j] = (j < G) ? Om[j * G + i] : T(0);
   }
+  float bom[NB];
+  if constexpr (MF)
+    if (MODE != PASS_B_EXPAND) mf_load_omega<NB>(mm, G, Om, bom);
   T treg[NIM][KV];
   {
     const T* tb = a.Tm + in.t_off + (int64_t)col * K + k0;
@@ -534,15 +666,27 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
       }
       sg.load();
     }
-    if (act) {
-      for (int t = r; t < nr; t += rpar) {
-        const size_t l = (size_t)t * P + i * K + k0;
-        const int64_t e = base + (int64_t)t * P + i * K + k0;
+    // rows t = r + it * rpar; the trip count is uniform across the workgroup
+    for (int it = 0; it * rpar < nr; ++it) {
+      const int t = r + it * rpar;
+      {
         T b[KV];
 #pragma unroll
         for (int v = 0; v < KV; ++v) b[v] = T(0);
+        if constexpr (MF) {
+          if (have_u) {
+            const mf4 acc = mf_apply<NB>(mm, Us, t - mm.tq, P, bom);
+#pragma unroll
+            for (int v = 0; v < KV; ++v) b[v] = acc[v];
+          }
+        }
+        if (!(act && t < nr)) continue;
+        const size_t l = (size_t)t * P + i * K + k0;
+        const int64_t e = base + (int64_t)t * P + i * K + k0;
         const T* urow = Us + (size_t)t * P + k0;
-        if (have_u) apply_omega<T, KV, KS, GR>(urow, K, G, i, om, Oms, b);
+        if constexpr (!MF) {
+          if (have_u) apply_omega<T, KV, KS, GR>(urow, K, G, i, om, Oms, b);
+        }
         T qt[KV];
 #pragma unroll
         for (int v = 0; v < KV; ++v) qt[v] = T(0);
@@ -609,7 +753,7 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
     }
   }
   if (MODE != PASS_B_EXPAND) {
-    reduce_k<KV>(cacc, on, K, KQ, reinterpret_cast<double*>(smem_raw), csum);
+    reduce_k<KV, MF>(cacc, on, K, KQ, reinterpret_cast<double*>(smem_raw), csum);
     if ((int)threadIdx.x < K) a.cpart[(int64_t)blockIdx.x * KMAX + threadIdx.x] = csum[threadIdx.x];
   }
   // algorithmic bytes: Q + (read w, write g, w); see pass A
@@ -695,6 +839,12 @@ template <typename T, int KV, int KS>
 hipError_t by_gr(const PassLaunch<T>& p, bool pass_a, int mode, hipStream_t s) {
   if (p.gr == 32) return by_nim<T, KV, KS, 32>(p, pass_a, mode, s);
   if (p.gr == 0) return by_nim<T, KV, KS, 0>(p, pass_a, mode, s);
+  // matrix-core Omega apply: FP32, sixteen rhs, G up to -gr
+  if constexpr (sizeof(T) == 4 && KV == 4 && KS == 16) {
+    if (p.gr == -16) return by_nim<T, KV, KS, -16>(p, pass_a, mode, s);
+    if (p.gr == -32) return by_nim<T, KV, KS, -32>(p, pass_a, mode, s);
+    if (p.gr == -64) return by_nim<T, KV, KS, -64>(p, pass_a, mode, s);
+  }
   return hipErrorInvalidValue;
 }
 
