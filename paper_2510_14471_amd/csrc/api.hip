@@ -28,8 +28,8 @@ constexpr size_t kAlign = 256;
 constexpr size_t kLdsBudget = 48 * 1024;  // dynamic LDS per workgroup (U and B slabs)
 constexpr size_t kRowOmegaLds = 64 * 1024; // largest Omega the row-vector passes stage in LDS
 constexpr int kRowsPerLane = 16;            // row-vector passes: rows per lane and sub-tile
-constexpr int kTargetTiles = 2048;        // row tiles over the whole batch
-constexpr int kMinTileRows = 64;          // keeps the per-tile partial sums small
+constexpr int kTargetTiles = 16384;       // row tiles over the whole batch (equal cost)
+constexpr int kMinTileRows = 16;          // keeps the per-tile partial sums small
 constexpr int kPollEvery = 8;             // iterations between host convergence polls
 // Stagnation windows: iterations in which c must at least halve.  Slowly
 // converging systems (singular Omega with a wide nonzero spectrum) need
@@ -175,7 +175,20 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
   p.prec = prec;
   int64_t sum_rows = 0;
   for (int b = 0; b < p.B; ++b) sum_rows += s->M[b];
-  int rc_rows = (int)std::max<int64_t>(kMinTileRows, (sum_rows + kTargetTiles - 1) / kTargetTiles);
+  // Row tiles of about equal streaming cost (Q row + three vector rows per
+  // observation), so that the workgroups of one launch finish together.
+  double total_cost = 0.0;
+  {
+    int64_t off = 0;
+    for (int b = 0; b < p.B; ++b) {
+      int64_t nb = 0;
+      for (int i = 0; i < s->G[b]; ++i) nb += s->n[off + i];
+      off += s->G[b];
+      total_cost += (double)s->M[b] * (double)(nb + 3 * (int64_t)s->G[b] * s->K[b]);
+    }
+  }
+  const double tile_cost = std::max(1.0, total_cost / kTargetTiles);
+  (void)sum_rows;
   // FP64 solves run in both modes (in the mixed path as the continuation of
   // a refinement the FP32 inner solves no longer advance)
   const bool need32 = prec == GLM_MIXED;
@@ -267,7 +280,9 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
     noff += in.G;
     // tiles: rows per tile a multiple of both sub-tile heights
     int step = std::max(std::max(in.rs_t[0], in.rs_t[1]), in.rs64);
-    int trows = std::max(step, (rc_rows + step - 1) / step * step);
+    const double row_cost = (double)(n + 3 * in.G * in.K);
+    const int want = std::max(kMinTileRows, (int)std::min(1e9, tile_cost / row_cost));
+    int trows = std::max(step, (want + step - 1) / step * step);
     in.tile0 = (int)p.tile.size();
     in.tp_stride = std::max<int64_t>(
         (int64_t)std::max(in.rpar_t[0], in.rpar_t[1]) * n * in.K, (int64_t)in.G * in.G);

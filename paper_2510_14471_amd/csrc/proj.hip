@@ -366,6 +366,8 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
     kq = pr - (pr / KQ) * KQ;
   }
   const int k0 = kq * KV;
+  // row stride of the lane's rows: the matrix-core mapping fixes it at 64 / Gp
+  const int rstep = MF ? mm.WPB * mm.RB : rpar;
   const BlockDesc bd = a.blks[in.blk0 + i];
   const int ni = bd.ni, col = bd.col;
   T om[GR > 0 ? GR : 1];
@@ -457,8 +459,8 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
       __syncthreads();
     }
     // rows t = r + it * rpar; the trip count is uniform across the workgroup
-    for (int it = 0; it * rpar < nr; ++it) {
-      const int t = r + it * rpar;
+    for (int it = 0; it * rstep < nr; ++it) {
+      const int t = r + it * rstep;
       {
         T b[KV];
 #pragma unroll
@@ -576,6 +578,8 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
     kq = pr - (pr / KQ) * KQ;
   }
   const int k0 = kq * KV;
+  // row stride of the lane's rows: the matrix-core mapping fixes it at 64 / Gp
+  const int rstep = MF ? mm.WPB * mm.RB : rpar;
   const BlockDesc bd = a.blks[in.blk0 + i];
   const int ni = bd.ni, col = bd.col;
   T om[GR > 0 ? GR : 1];
@@ -667,8 +671,8 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
       sg.load();
     }
     // rows t = r + it * rpar; the trip count is uniform across the workgroup
-    for (int it = 0; it * rpar < nr; ++it) {
-      const int t = r + it * rpar;
+    for (int it = 0; it * rstep < nr; ++it) {
+      const int t = r + it * rstep;
       {
         T b[KV];
 #pragma unroll
