@@ -92,7 +92,7 @@ PassCfg choose_cfg(const glm_shape* s, size_t sv, bool allow_rows) {
     c.ks = 16;
     c.gr = maxG <= 16 ? -16 : maxG <= 32 ? -32 : -64;
     c.rowpass = 1;
-    c.lds = ((size_t)PROJ_NT * (PROJ_NV * c.kv + PROJ_NQ) + PROJ_QPAD) * sv;
+    c.lds = ((size_t)PROJ_NT * (PROJ_NV * c.kv + PROJ_NQA) + PROJ_QPAD) * sv;
     return c;
   }
   // the Omega column in registers next to the projection slice, else in LDS
@@ -102,7 +102,7 @@ PassCfg choose_cfg(const glm_shape* s, size_t sv, bool allow_rows) {
   for (int b = 0; b < s->batch; ++b) fits = fits && s->G[b] * s->K[b] / c.kv <= PROJ_NT;
   c.rowpass = (fits && allow_rows) ? 1 : 0;
   if (c.rowpass)
-    c.lds = ((size_t)PROJ_NT * (PROJ_NV * c.kv + PROJ_NQ) + PROJ_QPAD) * sv +
+    c.lds = ((size_t)PROJ_NT * (PROJ_NV * c.kv + PROJ_NQA) + PROJ_QPAD) * sv +
             (c.gr == 0 ? (size_t)maxG * maxG * sv : 0);
   return c;
 }
@@ -226,6 +226,7 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
     for (int pi = 1; pi >= 0; --pi) {
       if (pi == 0 && !need32) {   // FP64 only: one configuration
         in.rs_t[0] = in.rs_t[1];
+        in.rsa_t[0] = in.rsa_t[1];
         in.rpar_t[0] = in.rpar_t[1];
         continue;
       }
@@ -247,8 +248,15 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
         rs = rs / rpar * rpar;   // whole rows per row group
         in.rs_t[pi] = std::max(rs, 1);
         in.rpar_t[pi] = rpar;
+        // pass A: two vector slabs and PROJ_NQA Q scalars per thread
+        const int rows_va = PROJ_NV * PROJ_NT * c.kv / (2 * P);
+        const int rows_qa = PROJ_NQA * PROJ_NT / n;
+        int rsa = std::min(std::min(rows_va, rows_qa), rpar * kRowsPerLane);
+        rsa = std::max(rsa / rpar * rpar, in.rs_t[pi]);
+        in.rsa_t[pi] = rsa;
       } else {
         in.rs_t[pi] = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * svp)));
+        in.rsa_t[pi] = in.rs_t[pi];
         in.rpar_t[pi] = 1;
         c.lds = std::max(c.lds, per_row * svp * in.rs_t[pi]);
       }
@@ -280,6 +288,7 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
     noff += in.G;
     // tiles: rows per tile a multiple of both sub-tile heights
     int step = std::max(std::max(in.rs_t[0], in.rs_t[1]), in.rs64);
+    step = std::max(step, std::max(in.rsa_t[0], in.rsa_t[1]));
     const double row_cost = (double)(n + 3 * in.G * in.K);
     const int want = std::max(kMinTileRows, (int)std::min(1e9, tile_cost / row_cost));
     int trows = std::max(step, (want + step - 1) / step * step);

@@ -29,6 +29,7 @@ struct InstDesc {
   int ntiles;
   int rs_t[2];     // rows per LDS-staged sub-tile of the passes (FP32, FP64)
   int rpar_t[2];   // row groups per workgroup of the passes (FP32, FP64)
+  int rsa_t[2];    // rows per sub-tile of pass A (FP32, FP64)
   int maxit;       // PCG iteration bound m - n + 1
   int rs64;        // rows per sub-tile for the double-precision residual pass
   int nimax;       // largest n_i of the instance
@@ -74,6 +75,10 @@ struct RhsState {
 template <typename T>
 __host__ __device__ inline int rows_of(const InstDesc& in) {
   return in.rs_t[sizeof(T) == 8];
+}
+template <typename T>
+__host__ __device__ inline int rows_a_of(const InstDesc& in) {
+  return in.rsa_t[sizeof(T) == 8];
 }
 template <typename T>
 __host__ __device__ inline int rpar_of(const InstDesc& in) {
@@ -123,6 +128,7 @@ struct PassLaunch {
 constexpr int PROJ_NT = 256;
 constexpr int PROJ_NV = 8;
 constexpr int PROJ_NQ = 8;
+constexpr int PROJ_NQA = 16;         // Q scalars per thread in pass A (two vector slabs)
 constexpr int PROJ_QPAD = QR_NMAX;   // zeros after the staged Q rows
 constexpr int kProjSliceRegs = 128;
 

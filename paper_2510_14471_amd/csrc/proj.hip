@@ -113,7 +113,7 @@ struct Args3 {
 // KV-wide chunks) followed by the Q slab of nr*n scalars and PROJ_QPAD
 // zeros.  LDS layout: [slab 0][slab 1][slab 2][Q rows][pad], slab s at
 // s*nr*P.
-template <typename T, int KV>
+template <typename T, int KV, int NQS = NQ>
 struct Stage3 {
   const T* v0;
   const T* v1;
@@ -123,7 +123,7 @@ struct Stage3 {
   int slab;      // elements per slab (nr * P)
   int qcnt;      // Q elements (nr * n)
   Vec<T, KV> rv[NV];
-  T rq[NQ];
+  T rq[NQS];
 
   __device__ __forceinline__ void load() {
     const int tid = threadIdx.x;
@@ -144,7 +144,7 @@ struct Stage3 {
       }
     }
 #pragma unroll
-    for (int s = 0; s < NQ; ++s) {
+    for (int s = 0; s < NQS; ++s) {
       const int e = tid + s * PNT;
       if (e < qcnt) rq[s] = gload1(q + e);
     }
@@ -159,7 +159,7 @@ struct Stage3 {
     }
     T* lq = lds + (size_t)nvec * slab;
 #pragma unroll
-    for (int s = 0; s < NQ; ++s) {
+    for (int s = 0; s < NQS; ++s) {
       const int e = tid + s * PNT;
       if (e < qcnt) lq[e] = rq[s];
     }
@@ -327,13 +327,15 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
   const TileDesc tile = a.tiles[blockIdx.x];
   if (!a.inst_active[tile.inst]) return;
   const InstDesc in = a.insts[tile.inst];
-  const int G = in.G, K = KS ? KS : in.K, n = in.n, rs = rows_of<T>(in), P = G * K, KQ = K / KV;
+  // pass A stages two vector slabs, so its sub-tiles take more Q rows
+  const int G = in.G, K = KS ? KS : in.K, n = in.n, rs = rows_a_of<T>(in), P = G * K,
+            KQ = K / KV;
   const int PP = G * KQ;           // lanes per row
   const int rpar = rpar_of<T>(in), nimax = in.nimax;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  T* Oms = lds + (size_t)PNT * (NV * KV + NQ) + PROJ_QPAD;   // Omega unless in registers
-  zero_lds(lds, PNT * (NV * KV + NQ) + PROJ_QPAD);
+  T* Oms = lds + (size_t)PNT * (NV * KV + PROJ_NQA) + PROJ_QPAD;   // Omega unless in registers
+  zero_lds(lds, PNT * (NV * KV + PROJ_NQA) + PROJ_QPAD);
   __shared__ double s_mu[KMAX];
   __shared__ int s_act[KMAX], s_first[KMAX];
   __shared__ double dsum[KMAX];
@@ -389,7 +391,7 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
   const bool have_y = (MODE == PASS_A_RHS) && a.y;
   const T* __restrict__ Qg = a.Q + in.q_off;
 
-  Stage3<T, KV> sg;
+  Stage3<T, KV, PROJ_NQA> sg;
   int sub = 0;
   {
     const int nr = min(rs, tile.rows);
