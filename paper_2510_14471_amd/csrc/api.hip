@@ -92,7 +92,8 @@ PassCfg choose_cfg(const glm_shape* s, size_t sv, bool allow_rows) {
     c.ks = 16;
     c.gr = maxG <= 16 ? -16 : maxG <= 32 ? -32 : -64;
     c.rowpass = 1;
-    c.lds = ((size_t)PROJ_NT * (PROJ_NV * c.kv + PROJ_NQA) + PROJ_QPAD) * sv;
+    c.lds = ((size_t)PROJ_NT * std::max(PROJ_NV * c.kv + PROJ_NQA, PROJ_NVB * c.kv + PROJ_NQB) +
+             PROJ_QPAD) * sv;
     return c;
   }
   // the Omega column in registers next to the projection slice, else in LDS
@@ -102,8 +103,8 @@ PassCfg choose_cfg(const glm_shape* s, size_t sv, bool allow_rows) {
   for (int b = 0; b < s->batch; ++b) fits = fits && s->G[b] * s->K[b] / c.kv <= PROJ_NT;
   c.rowpass = (fits && allow_rows) ? 1 : 0;
   if (c.rowpass)
-    c.lds = ((size_t)PROJ_NT * (PROJ_NV * c.kv + PROJ_NQA) + PROJ_QPAD) * sv +
-            (c.gr == 0 ? (size_t)maxG * maxG * sv : 0);
+    c.lds = ((size_t)PROJ_NT * std::max(PROJ_NV * c.kv + PROJ_NQA, PROJ_NVB * c.kv + PROJ_NQB) +
+             PROJ_QPAD) * sv + (c.gr == 0 ? (size_t)maxG * maxG * sv : 0);
   return c;
 }
 
@@ -239,8 +240,8 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
         const int rpar = c.gr < 0 ? 64 / gp : PROJ_NT / (P / c.kv);
         // rows per sub-tile: the three vector slabs of pass B and the Q rows
         // must fit the stager's per-thread registers
-        const int rows_v = PROJ_NV * PROJ_NT * c.kv / (3 * P);
-        const int rows_q = PROJ_NQ * PROJ_NT / n;
+        const int rows_v = PROJ_NVB * PROJ_NT * c.kv / (3 * P);
+        const int rows_q = PROJ_NQB * PROJ_NT / n;
         int rs = std::min(std::min(rows_v, rows_q), rpar * kRowsPerLane);
         // every row group needs a row per sub-tile; otherwise (wide Q rows,
         // few equations) the column-slot passes stream Q better

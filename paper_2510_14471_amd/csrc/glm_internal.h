@@ -129,6 +129,8 @@ constexpr int PROJ_NT = 256;
 constexpr int PROJ_NV = 8;
 constexpr int PROJ_NQ = 8;
 constexpr int PROJ_NQA = 16;         // Q scalars per thread in pass A (two vector slabs)
+constexpr int PROJ_NVB = 10;         // vector chunks per thread in pass B (three slabs)
+constexpr int PROJ_NQB = 10;         // Q scalars per thread in pass B
 constexpr int PROJ_QPAD = QR_NMAX;   // zeros after the staged Q rows
 constexpr int kProjSliceRegs = 128;
 

@@ -113,7 +113,7 @@ struct Args3 {
 // KV-wide chunks) followed by the Q slab of nr*n scalars and PROJ_QPAD
 // zeros.  LDS layout: [slab 0][slab 1][slab 2][Q rows][pad], slab s at
 // s*nr*P.
-template <typename T, int KV, int NQS = NQ>
+template <typename T, int KV, int NQS = NQ, int NVS = NV>
 struct Stage3 {
   const T* v0;
   const T* v1;
@@ -122,7 +122,7 @@ struct Stage3 {
   int nvec;      // number of vector slabs
   int slab;      // elements per slab (nr * P)
   int qcnt;      // Q elements (nr * n)
-  Vec<T, KV> rv[NV];
+  Vec<T, KV> rv[NVS];
   T rq[NQS];
 
   __device__ __forceinline__ void load() {
@@ -132,7 +132,7 @@ struct Stage3 {
     const uint64_t d1 = reinterpret_cast<uint64_t>(v1) - a0;
     const uint64_t d2 = reinterpret_cast<uint64_t>(v2) - reinterpret_cast<uint64_t>(v1);
 #pragma unroll
-    for (int s = 0; s < NV; ++s) {
+    for (int s = 0; s < NVS; ++s) {
       const int c = tid + s * PNT;           // chunk index over all slabs
       if (c < nvec * cps) {
         const bool s1 = c >= cps, s2 = c >= 2 * cps;
@@ -153,7 +153,7 @@ struct Stage3 {
     const int tid = threadIdx.x;
     const int cps = slab / KV;
 #pragma unroll
-    for (int s = 0; s < NV; ++s) {
+    for (int s = 0; s < NVS; ++s) {
       const int c = tid + s * PNT;
       if (c < nvec * cps) vstore<T, KV>(lds + (size_t)c * KV, rv[s]);
     }
@@ -545,8 +545,8 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
   const int rpar = rpar_of<T>(in), nimax = in.nimax;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  T* Oms = lds + (size_t)PNT * (NV * KV + NQ) + PROJ_QPAD;
-  zero_lds(lds, PNT * (NV * KV + NQ) + PROJ_QPAD);
+  T* Oms = lds + (size_t)PNT * (PROJ_NVB * KV + PROJ_NQB) + PROJ_QPAD;
+  zero_lds(lds, PNT * (PROJ_NVB * KV + PROJ_NQB) + PROJ_QPAD);
   __shared__ double s_lam[KMAX];
   __shared__ int s_act[KMAX];
   __shared__ double csum[KMAX];
@@ -609,7 +609,7 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
   const bool have_y = (MODE == PASS_B_INIT) && a.y;
   const T* __restrict__ Qg = a.Q + in.q_off;
 
-  Stage3<T, KV> sg;
+  Stage3<T, KV, PROJ_NQB, PROJ_NVB> sg;
   {
     const int nr = min(rs, tile.rows);
     const int64_t base = in.v_off + (int64_t)tile.row0 * P;
