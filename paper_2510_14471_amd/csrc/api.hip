@@ -714,7 +714,7 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
       // double-precision residual of the augmented system
       GLM_CHECK(launch_residual(f->d_inst(), f->d_tile(), p.ntiles, f->d_blk(),
                                 f->at<int>(p.o_colblk), f->d_active(), f->X, Om, y, u_out,
-                                beta_out, yf, f->at<double>(p.o_y64), f->at<double>(p.o_Tpart),
+                                beta_out, yf, nullptr, f->at<double>(p.o_Tpart),
                                 f->at<double>(p.o_cpart), f->at<double>(p.o_dpart), p.kc_t,
                                 p.sl, p.lds64, s));
       GLM_CHECK(launch_reduce_t<double>(f->d_inst(), f->d_tile(), f->d_active(),
@@ -767,6 +767,13 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
           if (log_on())
             std::fprintf(stderr, "[glm %.3fs] refinement step %d: %d instances continue in FP64\n",
                          now_s(), step, *f->h_count);
+          // the same residual again, kept in FP64, for the instances that continue in FP64
+          GLM_CHECK(launch_residual(f->d_inst(), f->d_tile(), p.ntiles, f->d_blk(),
+                                    f->at<int>(p.o_colblk), f->d_active(), f->X, Om, y, u_out,
+                                    beta_out, yf, f->at<double>(p.o_y64),
+                                    f->at<double>(p.o_Tpart), f->at<double>(p.o_cpart),
+                                    f->at<double>(p.o_dpart), p.kc_t, p.sl, p.lds64, s));
+          ++f->launches;
           double* w64 = f->at<double>(p.o_wf);
           int rc = core_solve<double>(f, f->at<double>(p.o_Q64), Om, f->at<double>(p.o_y64),
                                       f->at<double>(p.o_rho0), rhoc, w64, beta_out, true,
