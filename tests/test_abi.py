@@ -69,12 +69,39 @@ def test_shape_validation_and_workspace_sizes():
         _shape([1], [5], [1], [5]),                  # n >= G M (no null space)
         _shape([2], [50], [1], [0, 3]),              # n_i < 1
         _shape([1], [50], [1], [3], k=[4]),          # more restrictions than columns
+        _shape([], [], [], []),                      # empty batch
+        _shape([1], [0], [1], [1]),                  # no observations
+        _shape([0], [50], [1], []),                  # no equations
     ]
     for s in bad:
         assert _lib.glm_validate_shape(s) == _lib.GLM_EINVAL
         assert _lib.glm_workspace_bytes(s, _lib.GLM_FP64) == 0
-    wide = _shape([1], [500], [1], [65])             # block wider than the QR kernel
-    assert _lib.glm_validate_shape(wide) == _lib.GLM_EUNSUPPORTED
+    unsupported = [
+        _shape([1], [500], [1], [65]),               # block wider than the QR kernel
+        _shape([257], [10], [1], [1] * 257),         # Omega above 64k entries
+        _shape([40], [200], [1], [60] * 40),         # n above 2048 columns
+        _shape([2], [200], [1], [50, 50], k=[65]),   # more than 64 restrictions
+    ]
+    for s in unsupported:
+        assert _lib.glm_validate_shape(s) == _lib.GLM_EUNSUPPORTED
+        assert _lib.glm_workspace_bytes(s, _lib.GLM_FP64) == 0
+    # the largest accepted sizes plan a workspace
+    edge = _shape([256, 32], [40, 3000], [1, 16], [1] * 256 + [32] * 32, k=[0, 64])
+    assert _lib.glm_validate_shape(edge) == _lib.GLM_OK
+    assert _lib.glm_workspace_bytes(edge, _lib.GLM_MIXED) > 0
+
+
+def test_factor_rejects_a_short_workspace_before_any_device_work():
+    """The workspace check comes before any HIP call, so it runs without a GPU."""
+    import ctypes
+    from paper_2510_14471_amd import _lib
+    s = _shape([3], [200], [1], [4, 6, 5])
+    need = _lib.glm_workspace_bytes(s, _lib.GLM_FP64)
+    assert need > 0
+    out = ctypes.c_void_p()
+    rc = _lib._lib.glm_qr_factor(s.ptr(), _lib.GLM_FP64, ctypes.c_void_p(8), None,
+                                 ctypes.c_void_p(8), need - 1, None, ctypes.byref(out))
+    assert rc == _lib.GLM_EWORKSPACE and not out.value
 
 
 def test_strerror_is_total():
