@@ -108,8 +108,13 @@ typedef struct glm_stats {
 size_t glm_workspace_bytes(const glm_shape* shape, glm_precision prec);
 
 /* Checks a shape without touching the device.  Returns GLM_OK, GLM_EINVAL or
- * GLM_EUNSUPPORTED (e.g. n_b too large for K_b, see the limits in the
- * implementation notes). */
+ * GLM_EUNSUPPORTED.
+ *   GLM_EINVAL:  B < 1; G_b, M_b or n_{b,i} < 1; K_b outside 1..16; k_b < 0;
+ *                n_{b,i} > M_b; k_b > n_b; n_b >= G_b M_b + k_b (the augmented
+ *                system needs m + k > n).
+ *   GLM_EUNSUPPORTED (valid, outside this build's kernels): n_{b,i} > 64;
+ *                n_b > 2048, or n_b > 1024 with K_b > 4; k_b > 64;
+ *                G_b^2 > 65,536. */
 int glm_validate_shape(const glm_shape* shape);
 
 /* Factors every block once (SUR section: the data matrices are fixed, so
