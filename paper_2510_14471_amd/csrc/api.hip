@@ -122,14 +122,13 @@ struct Plan {
   int nrhs = 0, ntiles = 0, nblk = 0, maxK = 0, maxn = 0, maxni = 0, maxkc = 0;
   int kc_t = 1, sl = 1;
   // projection-pass configuration per arithmetic precision (index 0 = FP32
-  // inner solves of the mixed path, 1 = FP64 solves); lds64 is the residual pass
+  // inner solves of the mixed path, 1 = FP64 solves)
   PassCfg cfg[2];
-  size_t lds64 = 0;
   // byte offsets inside the workspace
   size_t o_Q64, o_Q32, o_R, o_Nb, o_colblk, o_inst, o_blk, o_tile, o_qrs, o_qrn, o_chunks,
       o_rinst, o_rinst_index, o_flags, o_active, o_icount, o_count, o_st, o_ost, o_alpha,
       o_Om32, o_g, o_u, o_wf, o_yf, o_y64, o_Tpart, o_Tm, o_dpart, o_cpart, o_gc, o_uc, o_wc,
-      o_wc64, o_rho0, o_rhoc, o_lb, o_bytes;
+      o_wc64, o_rho0, o_rhoc, o_lb, o_eye, o_mone, o_ypart, o_bytes;
   size_t total = 0;
 };
 
@@ -222,8 +221,6 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
     in.nb_off = p.sumNb;
     in.maxit = (int)std::min<int64_t>((int64_t)in.G * in.M + in.kc - n + 1, 1 << 30);
     const size_t per_row = 2 * (size_t)in.G * in.K;
-    in.rs64 = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * 8)));
-    p.lds64 = std::max(p.lds64, per_row * 8 * in.rs64);
     for (int pi = 1; pi >= 0; --pi) {
       if (pi == 0 && !need32) {   // FP64 only: one configuration
         in.rs_t[0] = in.rs_t[1];
@@ -288,7 +285,7 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
     }
     noff += in.G;
     // tiles: rows per tile a multiple of both sub-tile heights
-    int step = std::max(std::max(in.rs_t[0], in.rs_t[1]), in.rs64);
+    int step = std::max(in.rs_t[0], in.rs_t[1]);
     step = std::max(step, std::max(in.rsa_t[0], in.rsa_t[1]));
     const double row_cost = (double)(n + 3 * in.G * in.K);
     const int want = std::max(kMinTileRows, (int)std::min(1e9, tile_cost / row_cost));
@@ -394,6 +391,11 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
   p.o_rho0 = take(8 * p.sumnK);
   p.o_rhoc = take(8 * p.sumCK);
   p.o_lb = take(8 * p.sumnK);
+  // refinement residual by the FP64 passes: identity blocks, alpha = -1, and
+  // the per-tile partial norms of y (fixed over the refinement)
+  p.o_eye = take(prec == GLM_MIXED ? 8 * p.sumG2 : 0);
+  p.o_mone = take(prec == GLM_MIXED ? 8 * p.B : 0);
+  p.o_ypart = take(prec == GLM_MIXED ? 8 * (size_t)p.ntiles * KMAX : 0);
   p.o_bytes = take(2 * sizeof(unsigned long long));
   p.total = o;
   return GLM_OK;
@@ -709,21 +711,47 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
     GLM_CHECK(launch_fill<double>(wc64, std::max<int64_t>(p.sumCK, 0), 0.0, s));
     f->launches += 2;
     float* yf = f->at<float>(p.o_yf);
+    double* y64 = f->at<double>(p.o_y64);
+    double* Tm64 = f->at<double>(p.o_Tm);
+    GLM_CHECK(launch_eye(f->d_inst(), p.B, f->at<double>(p.o_eye), s));
+    GLM_CHECK(launch_fill<double>(f->at<double>(p.o_mone), p.B, -1.0, s));
+    f->launches += 2;
     int step = 0;
     for (step = 0; step <= kMaxOuter; ++step) {
-      // double-precision residual of the augmented system
-      GLM_CHECK(launch_residual(f->d_inst(), f->d_tile(), p.ntiles, f->d_blk(),
-                                f->at<int>(p.o_colblk), f->d_active(), f->X, Om, y, u_out,
-                                beta_out, yf, nullptr, f->at<double>(p.o_Tpart),
-                                f->at<double>(p.o_cpart), f->at<double>(p.o_dpart), p.kc_t,
-                                p.sl, p.lds64, s));
+      // Double-precision residual of the augmented system with the FP64
+      // passes, X in place of Q:
+      //   rho_y = y - W Omega - X beta   (pass B, INIT form, with T := beta
+      //           and alpha := -1; its c partials are ||rho_y||^2)
+      //   X^T W                          (pass A, RHS form, with y := 0 and
+      //           Omega := I, which yields -X^T W)
+      GLM_CHECK(launch_select_inner(f->d_inst(), p.B, f->d_st(), f->at<int>(p.o_ost),
+                                    f->d_active(), -2, s));
+      GLM_CHECK(launch_beta_to_t(f->d_inst(), p.B, beta_out, Tm64, s));
+      f->launches += 2;
+      {
+        PassLaunch<double> a = pass_args<double>(f, f->X, Om, y, u_out, y64, nullptr, false);
+        a.alpha = f->at<double>(p.o_mone);
+        a.w_nonzero = step > 0;
+        if (int rc = run_pass_b<double>(f, a, PASS_B_INIT, s)) return rc;
+      }
+      if (step == 0)   // rho_y = y: keep the partial norms of y
+        GLM_CHECK(hipMemcpyAsync(f->at<double>(p.o_ypart), f->at<double>(p.o_cpart),
+                                 8 * (size_t)p.ntiles * KMAX, hipMemcpyDeviceToDevice, s));
+      {
+        PassLaunch<double> a = pass_args<double>(f, f->X, f->at<double>(p.o_eye), nullptr,
+                                                 u_out, nullptr, nullptr, false);
+        a.w_nonzero = 1;
+        if (int rc = run_pass_a<double>(f, a, PASS_A_RHS, s)) return rc;
+      }
       GLM_CHECK(launch_reduce_t<double>(f->d_inst(), f->d_tile(), f->d_active(),
                                         f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
-                                        f->at<double>(p.o_Tpart), f->at<double>(p.o_Tm), 0, s));
+                                        f->at<double>(p.o_Tpart), Tm64,
+                                        p.cfg[1].rowpass, s));
+      GLM_CHECK(launch_to_float(y64, yf, p.sumMGK, s));
       GLM_CHECK(launch_outer_check(f->d_inst(), p.B, f->d_active(), f->d_st(),
                                    f->at<int>(p.o_ost), f->at<double>(p.o_cpart),
-                                   f->at<double>(p.o_dpart), f->at<double>(p.o_Tm), h2, f->Rc,
-                                   rvec, beta_out, wc64, f->at<double>(p.o_rho0),
+                                   f->at<double>(p.o_ypart), Tm64, -1.0, h2, f->Rc, rvec,
+                                   beta_out, wc64, f->at<double>(p.o_rho0),
                                    f->at<double>(p.o_rhoc), tol, step, step == kMaxOuter, s));
       f->launches += 3;
       // anything left?
@@ -767,15 +795,8 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
           if (log_on())
             std::fprintf(stderr, "[glm %.3fs] refinement step %d: %d instances continue in FP64\n",
                          now_s(), step, *f->h_count);
-          // the same residual again, kept in FP64, for the instances that continue in FP64
-          GLM_CHECK(launch_residual(f->d_inst(), f->d_tile(), p.ntiles, f->d_blk(),
-                                    f->at<int>(p.o_colblk), f->d_active(), f->X, Om, y, u_out,
-                                    beta_out, yf, f->at<double>(p.o_y64),
-                                    f->at<double>(p.o_Tpart), f->at<double>(p.o_cpart),
-                                    f->at<double>(p.o_dpart), p.kc_t, p.sl, p.lds64, s));
-          ++f->launches;
           double* w64 = f->at<double>(p.o_wf);
-          int rc = core_solve<double>(f, f->at<double>(p.o_Q64), Om, f->at<double>(p.o_y64),
+          int rc = core_solve<double>(f, f->at<double>(p.o_Q64), Om, y64,
                                       f->at<double>(p.o_rho0), rhoc, w64, beta_out, true,
                                       kInnerTol, kStallFP64, max_iter, s);
           if (rc) return rc;

@@ -1,9 +1,10 @@
 // Setup, iterative-refinement and gradient kernels around the PCG-Aug core.
 //
-//  * refinement (mixed precision): the double-precision residual of the
-//    augmented system  rho = [y - Sigma u - X beta ; h2 - X^T u]  read from X,
-//    not from the single-precision Q, then per (instance, rhs) the stopping
-//    test and the right-hand sides of the next inner solve;
+//  * refinement (mixed precision): from the double-precision residual of the
+//    augmented system  rho = [y - Sigma u - X beta ; h2 - X^T u]  (formed by
+//    the FP64 projection passes with X, not the single-precision Q, in place
+//    of Q), per (instance, rhs) the stopping test, the choice of the inner
+//    precision and the right-hand sides of the next inner solve;
 //  * gradients: dOmega = -sym(sum_t L_t U_t^T) (Kronecker-reduced outer
 //    products of the adjoint and primal u blocks) and dX_i = -(l_u,i beta_i^T
 //    + u_i l_beta,i^T), from the reverse rule of the augmented system.
@@ -103,153 +104,6 @@ __global__ void k_copy_tc(const InstDesc* __restrict__ insts, int B, const T* __
     wc[in.c_off + e] = (double)Tm[in.t_off + (int64_t)in.n * in.K + e];
 }
 
-// ---------------------------------------------------------------------------
-// double-precision refinement residual, one row tile per workgroup:
-//   rho_y = y - W Omega - [X_i beta_i]   (written in single precision for the
-//   inner solve), partial sums of ||rho_y||^2 and ||y||^2, and the partial
-//   column sums of X^T W.
-// ---------------------------------------------------------------------------
-struct ResArgs {
-  const InstDesc* __restrict__ insts;
-  const TileDesc* __restrict__ tiles;
-  const BlockDesc* __restrict__ blks;
-  const int* __restrict__ colblk;
-  const int* __restrict__ inst_active;
-  const double* __restrict__ X;
-  const double* __restrict__ Om;
-  const double* __restrict__ y;
-  const double* __restrict__ w;
-  const double* __restrict__ beta;
-  float* rho;
-  double* rho64;   // FP64 copy of rho_y (refinement continued in FP64), may be null
-  double* Tpart;
-  double* rpart;   // [tile][KMAX]  ||rho_y||^2
-  double* ypart;   // [tile][KMAX]  ||y||^2
-};
-
-template <int KC>
-__device__ void wg_reduce_store(double (&acc)[KC], int K, double* out, double* red) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    double s = wave_sum(acc[k]);
-    if (lane == 0) red[k * (NT / 64) + wv] = s;
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < K) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < NT / 64; ++q) s += red[threadIdx.x * (NT / 64) + q];
-    out[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
-template <int KC, int SL>
-__global__ void __launch_bounds__(NT) k_residual(ResArgs a) {
-  const TileDesc tile = a.tiles[blockIdx.x];
-  if (!a.inst_active[tile.inst]) return;
-  const InstDesc in = a.insts[tile.inst];
-  const int G = in.G, K = in.K, n = in.n, rs = in.rs64;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* Ws = reinterpret_cast<double*>(smem_raw);
-  double* Bs = Ws + (size_t)rs * G * K;
-  __shared__ double red[KC * (NT / 64)];
-  const double* __restrict__ Om = a.Om + in.om_off;
-  const double* __restrict__ Xb = a.X + in.q_off;
-  const double* __restrict__ bb = a.beta + in.b_off;
-  const int* __restrict__ cb = a.colblk + in.col_off;
-  const BlockDesc* __restrict__ bd = a.blks + in.blk0;
-  double tacc[SL][KC];
-#pragma unroll
-  for (int s = 0; s < SL; ++s)
-#pragma unroll
-    for (int k = 0; k < KC; ++k) tacc[s][k] = 0.0;
-  double racc[KC], yacc[KC];
-#pragma unroll
-  for (int k = 0; k < KC; ++k) racc[k] = yacc[k] = 0.0;
-  for (int sub = 0; sub < tile.rows; sub += rs) {
-    const int nr = min(rs, tile.rows - sub);
-    const int row = tile.row0 + sub;
-    const int64_t base = in.v_off + (int64_t)row * G * K;
-    const int cnt = nr * G * K;
-    for (int e = threadIdx.x; e < cnt; e += NT) Ws[e] = a.w[base + e];
-    __syncthreads();
-    for (int unit = threadIdx.x; unit < nr * G; unit += NT) {
-      const int t = unit / G, j = unit - t * G;
-      double acc[KC];
-#pragma unroll
-      for (int k = 0; k < KC; ++k) acc[k] = 0.0;
-      const double* wrow = Ws + (size_t)t * G * K;
-      for (int i = 0; i < G; ++i) {
-        const double om = Om[i * G + j];
-#pragma unroll
-        for (int k = 0; k < KC; ++k)
-          if (k < K) acc[k] += wrow[i * K + k] * om;
-      }
-#pragma unroll
-      for (int k = 0; k < KC; ++k)
-        if (k < K) Bs[((size_t)t * G + j) * K + k] = acc[k];
-    }
-    __syncthreads();
-    for (int unit = threadIdx.x; unit < nr * G; unit += NT) {
-      const int t = unit / G, i = unit - t * G;
-      const BlockDesc b = bd[i];
-      double xb[KC];
-#pragma unroll
-      for (int k = 0; k < KC; ++k) xb[k] = 0.0;
-      const double* xrow = Xb + (int64_t)(row + t) * n + b.col;
-      const double* brow = bb + (int64_t)b.col * K;
-      for (int c = 0; c < b.ni; ++c) {
-        const double x = xrow[c];
-#pragma unroll
-        for (int k = 0; k < KC; ++k)
-          if (k < K) xb[k] += x * brow[c * K + k];
-      }
-      const int64_t e0 = base + ((int64_t)t * G + i) * K;
-      const int l0 = (t * G + i) * K;
-#pragma unroll
-      for (int k = 0; k < KC; ++k)
-        if (k < K) {
-          const double yv = a.y ? a.y[e0 + k] : 0.0;
-          const double r = yv - Bs[l0 + k] - xb[k];
-          a.rho[e0 + k] = (float)r;
-          if (a.rho64) a.rho64[e0 + k] = r;
-          racc[k] += r * r;
-          yacc[k] += yv * yv;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      const int c = threadIdx.x + s * NT;
-      if (c < n) {
-        const int bi = cb[c];
-        const double* xcol = Xb + (int64_t)row * n + c;
-        for (int t = 0; t < nr; ++t) {
-          const double x = xcol[(int64_t)t * n];
-          const double* wr = Ws + ((size_t)t * G + bi) * K;
-#pragma unroll
-          for (int k = 0; k < KC; ++k)
-            if (k < K) tacc[s][k] += x * wr[k];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  double* tp = a.Tpart + tile.tp_off;
-#pragma unroll
-  for (int s = 0; s < SL; ++s) {
-    const int c = threadIdx.x + s * NT;
-    if (c < n) {
-#pragma unroll
-      for (int k = 0; k < KC; ++k)
-        if (k < K) tp[(int64_t)c * K + k] = tacc[s][k];
-    }
-  }
-  wg_reduce_store<KC>(racc, K, a.rpart + (int64_t)blockIdx.x * KMAX, red);
-  wg_reduce_store<KC>(yacc, K, a.ypart + (int64_t)blockIdx.x * KMAX, red);
-}
-
 // Per instance: rho_0 = h2 - X^T w - R_c^T wc, rho_c = r - R_c beta, the norms
 // and the outer stopping test.  Rhs that still need work become ST_ACTIVE for
 // the next inner solve, the others ST_IDLE; ost keeps the outer outcome.
@@ -257,7 +111,7 @@ __global__ void __launch_bounds__(NT)
 k_outer_check(const InstDesc* __restrict__ insts, int* __restrict__ inst_active,
               RhsState* __restrict__ st, int* __restrict__ ost,
               const double* __restrict__ rpart, const double* __restrict__ ypart,
-              const double* __restrict__ XtW, const double* __restrict__ h2,
+              const double* __restrict__ XtW, double xtw_sign, const double* __restrict__ h2,
               const double* __restrict__ Rc, const double* __restrict__ rvec,
               const double* __restrict__ beta, const double* __restrict__ wc,
               double* __restrict__ rho0, double* __restrict__ rhoc, double tol,
@@ -277,7 +131,7 @@ k_outer_check(const InstDesc* __restrict__ insts, int* __restrict__ inst_active,
     double acc_r = 0.0, acc_y = 0.0;
     for (int c = threadIdx.x; c < n; c += NT) {
       const int64_t bi = in.b_off + (int64_t)c * K + k;
-      double v = (h2 ? h2[bi] : 0.0) - XtW[in.t_off + (int64_t)c * K + k];
+      double v = (h2 ? h2[bi] : 0.0) - xtw_sign * XtW[in.t_off + (int64_t)c * K + k];
       for (int q = 0; q < kc; ++q)
         v -= Rc[in.rc_off + (int64_t)q * n + c] * wc[in.c_off + (int64_t)q * K + k];
       rho0[bi] = v;
@@ -521,37 +375,15 @@ template hipError_t launch_copy_tc<double>(const InstDesc*, int, const double*, 
 template hipError_t launch_copy_tc<float>(const InstDesc*, int, const float*, double*,
                                           hipStream_t);
 
-#define GLM_LAUNCH_RES(KCV, SLV)                                                          \
-  if (kc_t == KCV && sl == SLV) {                                                         \
-    hipLaunchKernelGGL((k_residual<KCV, SLV>), dim3(ntiles), dim3(NT), lds, s, a);        \
-    return hipGetLastError();                                                             \
-  }
-
-hipError_t launch_residual(const InstDesc* insts, const TileDesc* tiles, int ntiles,
-                           const BlockDesc* blks, const int* colblk, const int* inst_active,
-                           const double* X, const double* Om, const double* y,
-                           const double* w, const double* beta, float* rho, double* rho64,
-                           double* Tpart, double* rpart, double* ypart, int kc_t, int sl,
-                           size_t lds, hipStream_t s) {
-  ResArgs a{insts, tiles, blks, colblk, inst_active, X, Om, y, w, beta, rho, rho64, Tpart,
-            rpart, ypart};
-  GLM_LAUNCH_RES(1, 1) GLM_LAUNCH_RES(1, 2) GLM_LAUNCH_RES(1, 3) GLM_LAUNCH_RES(1, 4)
-  GLM_LAUNCH_RES(1, 8) GLM_LAUNCH_RES(2, 1) GLM_LAUNCH_RES(2, 2) GLM_LAUNCH_RES(2, 3)
-  GLM_LAUNCH_RES(2, 4) GLM_LAUNCH_RES(2, 8) GLM_LAUNCH_RES(4, 1) GLM_LAUNCH_RES(4, 2)
-  GLM_LAUNCH_RES(4, 3) GLM_LAUNCH_RES(4, 4) GLM_LAUNCH_RES(4, 8) GLM_LAUNCH_RES(8, 1)
-  GLM_LAUNCH_RES(8, 2) GLM_LAUNCH_RES(8, 3) GLM_LAUNCH_RES(8, 4) GLM_LAUNCH_RES(16, 1)
-  GLM_LAUNCH_RES(16, 2) GLM_LAUNCH_RES(16, 3) GLM_LAUNCH_RES(16, 4)
-  return hipErrorInvalidValue;
-}
-
 hipError_t launch_outer_check(const InstDesc* insts, int B, int* inst_active, RhsState* st,
                               int* ost, const double* rpart, const double* ypart,
-                              const double* XtW, const double* h2, const double* Rc,
+                              const double* XtW, double xtw_sign, const double* h2,
+                              const double* Rc,
                               const double* rvec, const double* beta, const double* wc,
                               double* rho0, double* rhoc, double tol, int step,
                               int last_step, hipStream_t s) {
   hipLaunchKernelGGL(k_outer_check, dim3(B), dim3(NT), 0, s, insts, inst_active, st, ost,
-                     rpart, ypart, XtW, h2, Rc, rvec, beta, wc, rho0, rhoc, tol, step,
+                     rpart, ypart, XtW, xtw_sign, h2, Rc, rvec, beta, wc, rho0, rhoc, tol, step,
                      last_step);
   return hipGetLastError();
 }
@@ -570,9 +402,40 @@ template hipError_t launch_update_u<double>(const InstDesc*, const TileDesc*, in
                                             const RhsState*, const double*, double*,
                                             hipStream_t);
 
+// beta (n x K per instance) into the projection layout ((n + k) x K per
+// instance), so that the expansion half of a pass forms X beta.
+__global__ void k_beta_to_t(const InstDesc* __restrict__ insts, int B,
+                            const double* __restrict__ beta, double* __restrict__ Tm) {
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const InstDesc in = insts[b];
+  for (int e = threadIdx.x; e < in.n * in.K; e += blockDim.x)
+    Tm[in.t_off + e] = beta[in.b_off + e];
+}
+
+hipError_t launch_beta_to_t(const InstDesc* insts, int B, const double* beta, double* Tm,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_beta_to_t, dim3(B), dim3(NT), 0, s, insts, B, beta, Tm);
+  return hipGetLastError();
+}
+
+// G x G identity per instance (the Omega of a pass that must not weight W).
+__global__ void k_eye(const InstDesc* __restrict__ insts, int B, double* __restrict__ E) {
+  const int b = blockIdx.x;
+  if (b >= B) return;
+  const InstDesc in = insts[b];
+  for (int e = threadIdx.x; e < in.G * in.G; e += blockDim.x)
+    E[in.om_off + e] = (e / in.G == e % in.G) ? 1.0 : 0.0;
+}
+
+hipError_t launch_eye(const InstDesc* insts, int B, double* E, hipStream_t s) {
+  hipLaunchKernelGGL(k_eye, dim3(B), dim3(NT), 0, s, insts, B, E);
+  return hipGetLastError();
+}
+
 // Mixed path: the rhs whose refinement continues take part in the next inner
-// solve of precision `want` (0 = FP32, 1 = FP64; -1 = all of them, which only
-// sets the instance activity for the refinement residual).
+// solve of precision `want` (0 = FP32, 1 = FP64); -2 selects all of them (the
+// refinement residual), -1 only sets the instance activity.
 __global__ void k_select_inner(const InstDesc* __restrict__ insts, int B,
                                RhsState* __restrict__ st, const int* __restrict__ ost,
                                int* __restrict__ inst_active, int want) {
@@ -583,7 +446,7 @@ __global__ void k_select_inner(const InstDesc* __restrict__ insts, int B,
   for (int k = 0; k < in.K; ++k) {
     RhsState& s = st[in.rhs0 + k];
     const bool on = ost[in.rhs0 + k] == ST_ACTIVE && (want < 0 || s.esc == want);
-    if (want >= 0 && s.status != ST_RANK) s.status = on ? ST_ACTIVE : ST_IDLE;
+    if (want != -1 && s.status != ST_RANK) s.status = on ? ST_ACTIVE : ST_IDLE;
     any |= on;
   }
   inst_active[b] = any;

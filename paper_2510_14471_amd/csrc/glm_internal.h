@@ -31,7 +31,6 @@ struct InstDesc {
   int rpar_t[2];   // row groups per workgroup of the passes (FP32, FP64)
   int rsa_t[2];    // rows per sub-tile of pass A (FP32, FP64)
   int maxit;       // PCG iteration bound m - n + 1
-  int rs64;        // rows per sub-tile for the double-precision residual pass
   int nimax;       // largest n_i of the instance
   int64_t tp_stride;  // elements per tile partial: max(rpar n K, G G)
   int64_t q_off;   // Q / X (M x n)
@@ -179,15 +178,10 @@ hipError_t launch_activate(const InstDesc* insts, int B, const RhsState* st, int
 template <typename T>
 hipError_t launch_copy_tc(const InstDesc* insts, int B, const T* Tm, double* wc,
                           hipStream_t s);
-hipError_t launch_residual(const InstDesc* insts, const TileDesc* tiles, int ntiles,
-                           const BlockDesc* blks, const int* colblk, const int* inst_active,
-                           const double* X, const double* Om, const double* y,
-                           const double* w, const double* beta, float* rho, double* rho64,
-                           double* Tpart, double* rpart, double* ypart, int kc_t, int sl,
-                           size_t lds, hipStream_t s);
 hipError_t launch_outer_check(const InstDesc* insts, int B, int* inst_active, RhsState* st,
                               int* ost, const double* rpart, const double* ypart,
-                              const double* XtW, const double* h2, const double* Rc,
+                              const double* XtW, double xtw_sign, const double* h2,
+                              const double* Rc,
                               const double* rvec, const double* beta, const double* wc,
                               double* rho0, double* rhoc, double tol, int step,
                               int last_step, hipStream_t s);
@@ -195,6 +189,9 @@ template <typename T>
 hipError_t launch_update_u(const InstDesc* insts, const TileDesc* tiles, int ntiles,
                            const int* inst_active, const RhsState* st, const T* du,
                            double* u, hipStream_t s);
+hipError_t launch_beta_to_t(const InstDesc* insts, int B, const double* beta, double* Tm,
+                            hipStream_t s);
+hipError_t launch_eye(const InstDesc* insts, int B, double* E, hipStream_t s);
 hipError_t launch_select_inner(const InstDesc* insts, int B, RhsState* st, const int* ost,
                                int* inst_active, int want, hipStream_t s);
 hipError_t launch_update_c(const InstDesc* insts, int B, const RhsState* st,
