@@ -102,3 +102,31 @@ def test_scaled_identity_omega_needs_one_iteration(glmlib):
                 o, ni = inst.col_off[i], inst.n_i[i]
                 ols = np.linalg.lstsq(inst.X(i), inst.Y[:, i, k], rcond=None)[0]
                 assert rel_err(out["beta"][b][o:o + ni, k], ols) < 1e-10
+
+
+def test_ill_conditioned_block_keeps_orthonormal_factors(glmlib):
+    """A block with two nearly collinear columns (condition ~1e7): the
+    Householder factors still come out orthonormal, reproduce X and count as
+    full rank (a Gram-based factorization would lose about eps cond^2)."""
+    inst = synth.small_batch(seed=73, B=1, G_rng=(3, 3), M_rng=(400, 400),
+                             n_rng=(4, 6), K_rng=(1, 1))[0]
+    rng = np.random.default_rng(3)
+    o = inst.col_off[1]
+    inst.W[:, o + 1] = inst.W[:, o] + 1e-7 * rng.standard_normal(inst.M)
+    lay, d = glmlib.pack_instances([inst])
+    s = glmlib.SURSolver(lay, "fp64")
+    s.factor(d["X"])
+    Q, R, rank = s.factors()
+    Q = glmlib.unpack(lay, Q, "X")[0]
+    R = R.cpu().numpy()
+    assert not rank.cpu().numpy().any()
+    eps = np.finfo(float).eps
+    ro = 0
+    for i in range(inst.G):
+        ni = inst.n_i[i]
+        Qi = Q[:, inst.col_off[i]:inst.col_off[i] + ni]
+        Ri = R[ro:ro + ni * ni].reshape(ni, ni)
+        ro += ni * ni
+        Xi = inst.X(i)
+        assert np.abs(Qi.T @ Qi - np.eye(ni)).max() <= 20 * ni * eps * np.sqrt(inst.M)
+        assert np.abs(Xi - Qi @ Ri).max() <= 20 * eps * np.abs(Xi).max() * np.sqrt(inst.M)
