@@ -199,6 +199,12 @@ __device__ void reduce_k(const double (&acc)[KV], bool on, int K, int KQ, double
 // (the staging area is zeroed at kernel start) and meet a zero Omega entry
 // (or an accumulator that is never stored, or a zero projection entry).
 constexpr int JC = 8;
+// Projection columns per uniform test in the Q T and Q^T B loops: twelve when
+// the n_i bound allows (more LDS reads in flight per batch), else eight.
+template <int NIM>
+constexpr int jcq() {
+  return NIM % 12 == 0 ? 12 : 8;
+}
 
 // b[v] += sum_{j < G} U[j][k0 + v] Omega[j][i] for the lane's right-hand-side
 // group, U[j] at urow + j*K.  With the stride K known at compile time the
@@ -497,10 +503,10 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
         // accumulators are never stored
         const T* qrow = Qs + (size_t)t * n + col;
 #pragma unroll
-        for (int c0 = 0; c0 < NIM; c0 += JC)
+        for (int c0 = 0; c0 < NIM; c0 += jcq<NIM>())
           if (c0 < nimax) {
 #pragma unroll
-            for (int c = c0; c < c0 + JC; ++c) {
+            for (int c = c0; c < c0 + jcq<NIM>(); ++c) {
               const T q = qrow[c];
 #pragma unroll
               for (int v = 0; v < KV; ++v) tacc[c][v] += q * b[v];
@@ -700,10 +706,10 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
         // entry or the zero pad
         const T* qrow = Qs + (size_t)t * n + col;
 #pragma unroll
-        for (int c0 = 0; c0 < NIM; c0 += JC)
+        for (int c0 = 0; c0 < NIM; c0 += jcq<NIM>())
           if (c0 < nimax) {
 #pragma unroll
-            for (int c = c0; c < c0 + JC; ++c) {
+            for (int c = c0; c < c0 + jcq<NIM>(); ++c) {
               const T q = qrow[c];
 #pragma unroll
               for (int v = 0; v < KV; ++v) qt[v] += q * treg[c][v];
