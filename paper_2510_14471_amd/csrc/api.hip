@@ -28,7 +28,7 @@ constexpr size_t kAlign = 256;
 constexpr size_t kLdsBudget = 48 * 1024;  // dynamic LDS per workgroup (U and B slabs)
 constexpr size_t kRowOmegaLds = 64 * 1024; // largest Omega the row-vector passes stage in LDS
 constexpr int kRowsPerLane = 16;            // row-vector passes: rows per lane and sub-tile
-constexpr int kTargetTiles = 16384;       // row tiles over the whole batch (equal cost)
+constexpr int kTargetTiles = 12288;       // row tiles over the whole batch (equal cost)
 constexpr int kMinTileRows = 16;          // keeps the per-tile partial sums small
 constexpr int kPollEvery = 8;             // iterations between host convergence polls
 // Stagnation windows: iterations in which c must at least halve.  Slowly

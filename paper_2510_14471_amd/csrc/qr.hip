@@ -228,6 +228,192 @@ k_qr(const QRJob* __restrict__ jobs, double* __restrict__ A,
   }
 }
 
+// The same factorization for blocks of at most 32 columns with the data
+// mapping turned around: lane l owns column l % 32, and the row slot
+// 2 w + l / 32 of wave w takes rows slot, slot + 8, ...  A row segment is then
+// one coalesced access, QR_U rows per lane are in flight at once, the dot
+// products are one register per lane, and the pivot-column entry of a row
+// comes from its lane by a shuffle.  Arithmetic and order of the updates
+// follow k_qr; only the summation order of the dot products differs.
+constexpr int QR_U = 8;                  // rows in flight per lane
+constexpr int QR_SLOTS = QNT / 32;       // row slots per workgroup
+
+// value of column col in the row this lane's half-wave holds
+__device__ __forceinline__ double shfl_col(double v, int col) {
+  return __shfl(v, (int)(threadIdx.x & 32) | col, 64);
+}
+
+// dsum[k] = sum of dot over the workgroup's lanes of column k, k in [lo, cols)
+__device__ __forceinline__ void col_sum(double dot, int lo, int cols, double (*red)[QW],
+                                        double* dsum) {
+  const int tid = threadIdx.x;
+  dot += __shfl_xor(dot, 32, 64);
+  if ((tid & 63) < 32) red[tid & 31][tid >> 6] = dot;
+  __syncthreads();
+  if (tid >= lo && tid < cols) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < QW; ++q) s += red[tid][q];
+    dsum[tid] = s;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(QNT)
+k_qr32(const QRJob* __restrict__ jobs, double* __restrict__ A, double* __restrict__ Rout,
+       int* __restrict__ flags) {
+  const QRJob job = jobs[blockIdx.x];
+  const int rows = job.rows, cols = job.cols, ld = job.ld;
+  double* __restrict__ a0 = A + job.a_off;
+
+  __shared__ double red[32][QW];
+  __shared__ double dsum[32];
+  __shared__ double pivrow[32];
+  __shared__ double wk[32];
+  __shared__ double tau_s[32];
+  __shared__ double par[3];
+  __shared__ double fro2;
+
+  const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
+  const bool colok = c < cols;
+
+  // ---- factorization: pass p applies reflector p-1 and builds reflector p --
+  for (int p = 0; p <= cols; ++p) {
+    const int j = p - 1;
+    const double beta_j = (p > 0) ? par[0] : 0.0;
+    const double tau_j = (p > 0) ? par[1] : 0.0;
+    const double scale_j = (p > 0) ? par[2] : 0.0;
+    const double wkc = (p > 0 && c > j && colok) ? wk[c] : 0.0;
+    const int lo = (j > 0) ? j : 0;
+    double dot = 0.0;
+    for (int t0 = lo; t0 < rows; t0 += QR_SLOTS * QR_U) {
+      double a[QR_U];
+#pragma unroll
+      for (int u = 0; u < QR_U; ++u) {
+        const int t = t0 + slot + QR_SLOTS * u;
+        a[u] = (t < rows && colok && c >= lo) ? a0[(int64_t)t * ld + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < QR_U; ++u) {
+        const int t = t0 + slot + QR_SLOTS * u;
+        const bool rok = t < rows;
+        double x = a[u];
+        if (p > 0) {
+          const double aj = shfl_col(x, j);
+          const double vv = (t > j) ? aj * scale_j : 1.0;   // reflector j at row t
+          if (c > j) x -= tau_j * vv * wkc;
+          if (c == j) x = (t == j) ? beta_j : vv;
+          if (rok && colok && c >= j) a0[(int64_t)t * ld + c] = x;
+        }
+        if (p < cols) {
+          if (rok && t == p && colok && c >= p) pivrow[c] = x;
+          // dot products of the subcolumn below the pivot with every column
+          const double ap = shfl_col(x, p);
+          if (rok && t > p && c >= p) dot += ap * x;
+        }
+      }
+    }
+    if (p == cols) break;
+    __syncthreads();  // pivrow visible, all rows written
+    col_sum(dot, p, cols, red, dsum);
+    if (tid == 0) {
+      const double alpha = pivrow[p];
+      const double xnorm2 = dsum[p];            // squared norm below the pivot
+      const double nrm2 = alpha * alpha + xnorm2;
+      double beta, tau, scale;
+      if (!(xnorm2 > 0.0)) {
+        beta = alpha;  // H = I (LAPACK: tau = 0 when the subcolumn is zero)
+        tau = 0.0;
+        scale = 0.0;
+      } else {
+        const double nrm = sqrt(nrm2);
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      par[0] = beta;
+      par[1] = tau;
+      par[2] = scale;
+      tau_s[p] = tau;
+      for (int k = p + 1; k < cols; ++k)
+        wk[k] = pivrow[k] + scale * dsum[k];    // v^T a_k with v = [1; x * scale]
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+
+  // ---- R out (upper triangle of the first cols rows), rank check ---------
+  if (tid == 0) fro2 = 0.0;
+  __syncthreads();
+  double loc = 0.0;
+  for (int e = tid; e < cols * cols; e += QNT) {
+    const int r = e / cols, cc = e % cols;
+    const double v = (cc >= r) ? a0[(int64_t)r * ld + cc] : 0.0;
+    if (job.r_off >= 0) Rout[job.r_off + e] = v;
+    loc += v * v;
+  }
+  loc = wave_sum(loc);
+  if ((tid & 63) == 0) atomicAdd(&fro2, loc);
+  __syncthreads();
+  if (tid == 0) {
+    const double tolr = 2.220446049250313e-16 * (double)(rows > cols ? rows : cols) *
+                        sqrt(fro2);
+    int bad = 0;
+    for (int r = 0; r < cols; ++r)
+      if (!(fabs(a0[(int64_t)r * ld + r]) > tolr)) bad = 1;
+    if (job.flag >= 0) flags[job.flag] = bad;
+  }
+  __syncthreads();
+
+  // ---- explicit thin Q, backward accumulation of the reflectors ---------
+  for (int j = cols - 1; j >= 0; --j) {
+    const double tau_j = tau_s[j];
+    const double wkc = (j < cols - 1 && c > j && colok) ? wk[c] : 0.0;
+    const int lo = (j > 0) ? j - 1 : 0;
+    double dot = 0.0;
+    // rows above lo: column j becomes zero (row j-1 is handled in the sweep)
+    for (int t = tid; t < lo && t < rows; t += QNT) a0[(int64_t)t * ld + j] = 0.0;
+    for (int t0 = lo; t0 < rows; t0 += QR_SLOTS * QR_U) {
+      double a[QR_U];
+#pragma unroll
+      for (int u = 0; u < QR_U; ++u) {
+        const int t = t0 + slot + QR_SLOTS * u;
+        a[u] = (t < rows && colok && c >= lo) ? a0[(int64_t)t * ld + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < QR_U; ++u) {
+        const int t = t0 + slot + QR_SLOTS * u;
+        const bool rok = t < rows;
+        double x = a[u];
+        // columns j and j-1 of this row as loaded (this pass changes columns >= j)
+        const double xj = shfl_col(x, j);
+        const double xjm = shfl_col(x, j >= 1 ? j - 1 : 0);
+        if (t >= j) {
+          const double vj = (t > j) ? xj : 1.0;
+          if (c > j) x -= tau_j * vj * wkc;
+          if (c == j) x = (t > j) ? -tau_j * vj : 1.0 - tau_j;
+          if (rok && colok && c >= j) a0[(int64_t)t * ld + c] = x;
+        } else {
+          // t == j - 1: above the diagonal of column j
+          if (c == j) x = 0.0;
+          if (rok && c == j) a0[(int64_t)t * ld + j] = 0.0;
+        }
+        if (j >= 1) {
+          // reflector j-1: v[j-1] = 1, v[t] = a[j-1] below
+          const double vjm = (t == j - 1) ? 1.0 : xjm;
+          if (rok && c >= j) dot += vjm * x;
+        }
+      }
+    }
+    __syncthreads();
+    if (j >= 1) {
+      col_sum(dot, j, cols, red, dsum);
+      if (tid >= j && tid < cols) wk[tid] = dsum[tid];
+      __syncthreads();
+    }
+  }
+}
+
 __global__ void k_to_float(const double* __restrict__ src, float* __restrict__ dst,
                            int64_t count) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
@@ -274,12 +460,8 @@ __global__ void k_nullbasis_input(const InstDesc* __restrict__ insts,
 hipError_t launch_qr(const QRJob* d_jobs, int njobs, int nmax, double* A,
                      double* R, int* flags, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
-  if (nmax <= 8)
-    hipLaunchKernelGGL(k_qr<8>, dim3(njobs), dim3(QNT), 0, s, d_jobs, A, R, flags);
-  else if (nmax <= 16)
-    hipLaunchKernelGGL(k_qr<16>, dim3(njobs), dim3(QNT), 0, s, d_jobs, A, R, flags);
-  else if (nmax <= 32)
-    hipLaunchKernelGGL(k_qr<32>, dim3(njobs), dim3(QNT), 0, s, d_jobs, A, R, flags);
+  if (nmax <= 32)
+    hipLaunchKernelGGL(k_qr32, dim3(njobs), dim3(QNT), 0, s, d_jobs, A, R, flags);
   else
     hipLaunchKernelGGL(k_qr<64>, dim3(njobs), dim3(QNT), 0, s, d_jobs, A, R, flags);
   return hipGetLastError();
