@@ -468,3 +468,48 @@ def test_planted_mistake_inverted_mu_is_caught():
         c = c_new
     z_wrong = ops.Xstar_T(y - ops.Sigma(w))
     assert rel_err(z_wrong, beta[:, 0]) > 1e-6
+
+
+# -- SUR model reduction: the reduced route is the GLS of the full model ----------
+
+def test_model_reduction_preserves_gls():
+    """The GLS of the reduced model (one QR of W = [X_1 ... X_G]) equals the
+    direct GLS of the full model, beta and u, with and without restrictions,
+    and when M < n + 1 leaves nothing to drop."""
+    from oracle import reduce as ored
+    insts = list(synth.small_batch(seed=31, B=4, G_rng=(1, 5), M_rng=(30, 200),
+                                   n_rng=(1, 6), K_rng=(1, 3)))
+    insts += list(synth.small_batch(seed=33, B=3, G_rng=(2, 4), M_rng=(40, 90),
+                                    n_rng=(2, 5), K_rng=(1, 2), constraints=3))
+    insts += list(synth.small_batch(seed=35, B=1, G_rng=(6, 6), M_rng=(9, 9),
+                                    n_rng=(2, 3), K_rng=(2, 2)))
+    for inst in insts:
+        Mr = ored.reduced_rows(inst.M, inst.n)
+        assert Mr == min(inst.M, inst.n + 1)
+        beta_r, U_r = ored.sur_gls_reduced(inst)
+        if inst.Rc is not None:
+            beta_d, U_d, _ = gls.restricted_gls(inst)
+        else:
+            beta_d, U_d = gls.sur_gls(inst)
+        assert rel_err(beta_r, beta_d) < 1e-11
+        assert rel_err(U_r, U_d) < 1e-11
+
+
+def test_model_reduction_drops_only_noise_rows():
+    """Rotated regressors vanish below row n; the dropped rows still carry the
+    part of u that the tail term (Q^T Y) Omega^-1 restores: leaving it out
+    changes u but not beta."""
+    from oracle import reduce as ored
+    inst = synth.small_batch(seed=37, B=1, G_rng=(3, 3), M_rng=(60, 60),
+                             n_rng=(2, 4), K_rng=(2, 2))[0]
+    red, Q, QtY = ored.reduce_instance(inst)
+    QtW = Q.T @ inst.W
+    assert np.abs(QtW[inst.n:]).max() < 1e-12 * np.abs(inst.W).max()
+    assert np.allclose(Q.T @ Q, np.eye(inst.M), atol=1e-13)
+    beta_r, Ur = gls.sur_gls(red)
+    beta_d, U_d = gls.sur_gls(inst)
+    assert rel_err(beta_r, beta_d) < 1e-11
+    Z = np.zeros_like(inst.Y)
+    Z[:red.M] = Ur
+    U_no_tail = np.einsum("ts,sik->tik", Q, Z)
+    assert rel_err(U_no_tail, U_d) > 1e-2
