@@ -77,10 +77,24 @@ extern "C" {
 
 typedef enum glm_precision {
   GLM_FP64 = 0,   /* every step in double precision                               */
-  GLM_MIXED = 1   /* inner PCG with single-precision Q_i, vectors and Omega
+  GLM_MIXED = 1,  /* inner PCG with single-precision Q_i, vectors and Omega
                      (single-precision accumulation, double-precision dot
                      products), inside double-precision iterative refinement;
                      QR, refinement residual and the beta/u updates in double   */
+  GLM_REDUCED = 4 /* flag, OR-ed into GLM_FP64 or GLM_MIXED for
+                     glm_workspace_bytes and glm_qr_factor: SUR model reduction
+                     (the remark on reducing the SUR model in the SUR section).
+                     One Householder QR of W = [X_1 ... X_G] = Q [R; 0] per
+                     instance (double precision) rotates every equation by Q^T;
+                     the solve then runs PCG-Aug on the first min(M, n + 1)
+                     rotated observations, which give the GLS estimate of the
+                     full model, and returns beta and u of the full model
+                     (u = Q [u_reduced; (Q^T Y)_{rest} Omega^-1]).  Requires a
+                     positive definite Omega (otherwise the instance's rhs
+                     report GLM_INFO_BREAKDOWN) and G_b <= 64 (otherwise
+                     GLM_EUNSUPPORTED).  glm_gls_backward and
+                     glm_copy_factors return GLM_EUNSUPPORTED on such a
+                     handle.                                                     */
 } glm_precision;
 
 typedef struct glm_shape {

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libglm_hip.so")
 
 GLM_FP64 = 0
 GLM_MIXED = 1
+GLM_REDUCED = 4      # flag OR-ed into the precision: SUR model reduction
 
 GLM_OK = 0
 GLM_EINVAL = -1

@@ -408,8 +408,103 @@ struct EventPair {
 
 }  // namespace
 
+namespace {
+
+// Model reduction: per-instance descriptors, the reduced shape (the same
+// equations and blocks with min(M, n + 1) observations) and the layout of
+// the reduction buffers, followed by the reduced problem's own workspace.
+struct RedPlan {
+  int B = 0, maxpan = 0;
+  std::vector<RedDesc> d;
+  std::vector<int32_t> G, M, K, k, n;
+  glm_shape sub{};
+  int64_t sumMn = 0, sumMGK = 0, sumMrn = 0, sumMrGK = 0, sumn = 0, sumT = 0;
+  size_t o_desc = 0, o_W = 0, o_tau = 0, o_T = 0, o_Yt = 0, o_Xr = 0, o_yr = 0, o_ur = 0,
+         o_sub = 0, sub_bytes = 0, total = 0;
+};
+
+int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
+  int rc = validate(s);
+  if (rc != GLM_OK) return rc;
+  r = RedPlan();
+  r.B = s->batch;
+  int64_t noff = 0, rhs = 0, om = 0;
+  for (int b = 0; b < r.B; ++b) {
+    // the Omega^-1 of the dropped rows is formed in LDS for G <= 64
+    if (s->G[b] > 64) return GLM_EUNSUPPORTED;
+    RedDesc d{};
+    d.M = s->M[b];
+    d.G = s->G[b];
+    d.K = s->K[b];
+    int n = 0;
+    for (int i = 0; i < d.G; ++i) n += s->n[noff + i];
+    d.n = n;
+    d.Mr = std::min(d.M, n + 1);
+    d.kr = std::min(d.M, n);
+    d.rhs0 = (int)rhs;
+    d.w_off = r.sumMn;
+    d.v_off = r.sumMGK;
+    d.xr_off = r.sumMrn;
+    d.vr_off = r.sumMrGK;
+    d.tau_off = r.sumn;
+    d.t_off = r.sumT;
+    d.om_off = om;
+    const int npan = (d.kr + RED_PANEL - 1) / RED_PANEL;
+    r.maxpan = std::max(r.maxpan, npan);
+    r.sumMn += (int64_t)d.M * n;
+    r.sumMGK += (int64_t)d.M * d.G * d.K;
+    r.sumMrn += (int64_t)d.Mr * n;
+    r.sumMrGK += (int64_t)d.Mr * d.G * d.K;
+    r.sumn += n;
+    r.sumT += (int64_t)npan * RED_PANEL * RED_PANEL;
+    om += (int64_t)d.G * d.G;
+    rhs += d.K;
+    r.d.push_back(d);
+    r.G.push_back(d.G);
+    r.M.push_back(d.Mr);
+    r.K.push_back(d.K);
+    r.k.push_back(s->k ? s->k[b] : 0);
+    noff += d.G;
+  }
+  r.n.assign(s->n, s->n + noff);
+  r.sub.batch = r.B;
+  r.sub.G = r.G.data();
+  r.sub.M = r.M.data();
+  r.sub.K = r.K.data();
+  r.sub.k = r.k.data();
+  r.sub.n = r.n.data();
+  rc = validate(&r.sub);
+  if (rc != GLM_OK) return rc;
+  Plan sp;
+  rc = make_plan(&r.sub, base, sp);
+  if (rc != GLM_OK) return rc;
+  r.sub_bytes = sp.total;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  r.o_desc = take(sizeof(RedDesc) * r.d.size());
+  r.o_W = take(8 * r.sumMn);
+  r.o_tau = take(8 * r.sumn);
+  r.o_T = take(8 * r.sumT);
+  r.o_Yt = take(8 * r.sumMGK);
+  r.o_Xr = take(8 * r.sumMrn);
+  r.o_yr = take(8 * r.sumMrGK);
+  r.o_ur = take(8 * r.sumMrGK);
+  r.o_sub = take(r.sub_bytes);
+  r.total = o;
+  return GLM_OK;
+}
+
+}  // namespace
+
 struct glm_factor {
   Plan p;
+  bool reduced = false;
+  RedPlan rp;
+  glm_factor* sub = nullptr;   // factor of the reduced problem
   char* ws = nullptr;
   const double* X = nullptr;
   const double* Rc = nullptr;
@@ -826,11 +921,102 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
 // C ABI
 // ---------------------------------------------------------------------------
 
+namespace {
+
+// glm_qr_factor with GLM_REDUCED: copy X, factor W = [X_1 ... X_G] panel by
+// panel (each panel's block reflector applied to the columns right of it),
+// take the reduced regressors from R and factor the reduced problem in the
+// rest of the workspace.
+int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
+                   const double* Rc, void* ws, size_t ws_bytes, hipStream_t stream,
+                   glm_factor** out) {
+  glm_factor* f = new (std::nothrow) glm_factor();
+  if (!f) return GLM_EINVAL;
+  int rc = make_red_plan(shape, base, f->rp);
+  if (rc != GLM_OK) {
+    delete f;
+    return rc;
+  }
+  const RedPlan& r = f->rp;
+  bool any_k = false;
+  for (int32_t v : r.k) any_k = any_k || v > 0;
+  if (any_k && !Rc) {
+    delete f;
+    return GLM_EINVAL;
+  }
+  if (!ws || ws_bytes < r.total) {
+    delete f;
+    return GLM_EWORKSPACE;
+  }
+  f->reduced = true;
+  f->ws = static_cast<char*>(ws);
+  f->X = X;
+  f->Rc = Rc;
+  const RedDesc* dd = f->at<RedDesc>(r.o_desc);
+  double* W = f->at<double>(r.o_W);
+  double* T = f->at<double>(r.o_T);
+  hipError_t e = hipMemcpyAsync(f->ws + r.o_desc, r.d.data(), sizeof(RedDesc) * r.d.size(),
+                                hipMemcpyHostToDevice, stream);
+  if (!e) e = hipMemcpyAsync(W, X, 8 * r.sumMn, hipMemcpyDeviceToDevice, stream);
+  for (int p = 0; p < r.maxpan && !e; ++p) {
+    e = launch_red_panel(dd, r.B, p, W, f->at<double>(r.o_tau), T, stream);
+    if (!e) e = launch_red_apply(dd, r.B, p, W, T, W, 1, 1, stream);
+  }
+  if (!e) e = launch_red_extract(dd, r.B, W, nullptr, f->at<double>(r.o_Xr), nullptr, stream);
+  if (e != hipSuccess) {
+    delete f;
+    return GLM_EHIP;
+  }
+  rc = glm_qr_factor(&f->rp.sub, base, f->at<double>(r.o_Xr), Rc, f->ws + r.o_sub,
+                     r.sub_bytes, stream, &f->sub);
+  if (rc != GLM_OK) {
+    delete f;
+    return rc;
+  }
+  *out = f;
+  return GLM_OK;
+}
+
+// glm_gls_solve on a reduced handle: Y -> Q^T Y, the reduced solve on its
+// first Mr rows, then u = Q [u_reduced ; (Q^T Y)_{t >= Mr} Omega^-1].
+int solve_reduced(glm_factor* f, const double* Omega, const double* y, const double* r,
+                  double tol, int32_t max_iter, double* beta, double* u, double* uc,
+                  int32_t* info, int32_t* iters, hipStream_t stream) {
+  const RedPlan& rp = f->rp;
+  const RedDesc* dd = f->at<RedDesc>(rp.o_desc);
+  const double* W = f->at<double>(rp.o_W);
+  const double* T = f->at<double>(rp.o_T);
+  double* Yt = f->at<double>(rp.o_Yt);
+  double* ur = f->at<double>(rp.o_ur);
+  GLM_CHECK(hipMemcpyAsync(Yt, y, 8 * rp.sumMGK, hipMemcpyDeviceToDevice, stream));
+  for (int p = 0; p < rp.maxpan; ++p)
+    GLM_CHECK(launch_red_apply(dd, rp.B, p, W, T, Yt, 0, 1, stream));
+  GLM_CHECK(launch_red_extract(dd, rp.B, W, Yt, nullptr, f->at<double>(rp.o_yr), stream));
+  int rc = glm_gls_solve(f->sub, Omega, f->at<double>(rp.o_yr), r, tol, max_iter, beta, ur, uc,
+                         info, iters, stream);
+  if (rc != GLM_OK) return rc;
+  GLM_CHECK(launch_red_tail(dd, rp.B, Omega, Yt, ur, u, info, stream));
+  for (int p = rp.maxpan - 1; p >= 0; --p)
+    GLM_CHECK(launch_red_apply(dd, rp.B, p, W, T, u, 0, 0, stream));
+  f->stats = f->sub->stats;
+  f->stats.launches += 2 * rp.maxpan + 2;
+  return GLM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int glm_validate_shape(const glm_shape* shape) { return validate(shape); }
 
 size_t glm_workspace_bytes(const glm_shape* shape, glm_precision prec) {
+  if ((int)prec & GLM_REDUCED) {
+    const glm_precision base = (glm_precision)((int)prec & ~GLM_REDUCED);
+    if (base != GLM_FP64 && base != GLM_MIXED) return 0;
+    RedPlan r;
+    if (make_red_plan(shape, base, r) != GLM_OK) return 0;
+    return r.total;
+  }
   if (prec != GLM_FP64 && prec != GLM_MIXED) return 0;
   Plan p;
   if (make_plan(shape, prec, p) != GLM_OK) return 0;
@@ -842,6 +1028,11 @@ int glm_qr_factor(const glm_shape* shape, glm_precision prec, const double* X,
                   glm_factor** out) {
   if (!out || !X) return GLM_EINVAL;
   *out = nullptr;
+  if ((int)prec & GLM_REDUCED) {
+    const glm_precision base = (glm_precision)((int)prec & ~GLM_REDUCED);
+    if (base != GLM_FP64 && base != GLM_MIXED) return GLM_EINVAL;
+    return factor_reduced(shape, base, X, Rc, ws, ws_bytes, stream, out);
+  }
   if (prec != GLM_FP64 && prec != GLM_MIXED) return GLM_EINVAL;
   glm_factor* f = new (std::nothrow) glm_factor();
   if (!f) return GLM_EINVAL;
@@ -910,8 +1101,10 @@ int glm_gls_solve(glm_factor* f, const double* Omega, const double* y, const dou
                   double tol, int32_t max_iter, double* beta, double* u, double* uc,
                   int32_t* info, int32_t* iters, hipStream_t stream) {
   if (!f || !Omega || !y || !beta || !u) return GLM_EINVAL;
-  if (f->p.sumCK > 0 && !r) return GLM_EINVAL;
   if (!(tol >= 0.0)) return GLM_EINVAL;
+  if (f->reduced)
+    return solve_reduced(f, Omega, y, r, tol, max_iter, beta, u, uc, info, iters, stream);
+  if (f->p.sumCK > 0 && !r) return GLM_EINVAL;
   return solve_driver(f, Omega, y, nullptr, r, tol, max_iter, beta, u, uc, info, iters, stream);
 }
 
@@ -921,6 +1114,7 @@ int glm_gls_backward(glm_factor* f, const double* Omega, const double* beta, con
                      hipStream_t stream) {
   if (!f || !Omega || !beta || !u || !g_beta || !dy) return GLM_EINVAL;
   if (!(tol >= 0.0)) return GLM_EINVAL;
+  if (f->reduced) return GLM_EUNSUPPORTED;
   const Plan& p = f->p;
   double* lb = f->at<double>(p.o_lb);
   // adjoint system [Sigma X; X^T 0][l_u; l_beta] = [g_u; g_beta] (restriction rows: 0)
@@ -936,6 +1130,7 @@ int glm_gls_backward(glm_factor* f, const double* Omega, const double* beta, con
 int glm_copy_factors(const glm_factor* f, double* Q, double* R, int32_t* rank,
                      hipStream_t stream) {
   if (!f) return GLM_EINVAL;
+  if (f->reduced) return GLM_EUNSUPPORTED;
   const Plan& p = f->p;
   if (Q)
     GLM_CHECK(hipMemcpyAsync(Q, f->ws + p.o_Q64, 8 * p.sumMn, hipMemcpyDeviceToDevice, stream));
@@ -955,6 +1150,7 @@ int glm_get_stats(const glm_factor* f, glm_stats* out) {
 
 int glm_profile_enable(glm_factor* f, int on) {
   if (!f) return GLM_EINVAL;
+  if (f->reduced) return glm_profile_enable(f->sub, on);
   f->prof = on != 0;
   return GLM_OK;
 }
@@ -962,6 +1158,7 @@ int glm_profile_enable(glm_factor* f, int on) {
 int glm_profile_read(glm_factor* f, int kernel_id, int64_t* launches, double* total_ms,
                      double* total_bytes) {
   if (!f || kernel_id < 0 || kernel_id > 1) return GLM_EINVAL;
+  if (f->reduced) return glm_profile_read(f->sub, kernel_id, launches, total_ms, total_bytes);
   if (hipDeviceSynchronize() != hipSuccess) return GLM_EHIP;
   for (auto& e : f->ev_used) {
     float ms = 0.f;
@@ -988,6 +1185,7 @@ int glm_profile_read(glm_factor* f, int kernel_id, int64_t* launches, double* to
 
 void glm_factor_destroy(glm_factor* f) {
   if (!f) return;
+  if (f->sub) glm_factor_destroy(f->sub);
   for (auto& e : f->ev_used) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);

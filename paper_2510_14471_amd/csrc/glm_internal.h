@@ -88,6 +88,24 @@ struct RedChunk {
   int inst, p0;
 };
 
+// Model reduction of one SUR instance: W = [X_1 ... X_G] = Q [R; 0] by
+// Householder panels of 32 columns; the reduced model keeps Mr = min(M, n + 1)
+// rotated observations.
+struct RedDesc {
+  int M, n, G, K, Mr;
+  int kr;          // reflectors: min(M, n)
+  int rhs0;        // first (instance, rhs) index
+  int pad;
+  int64_t w_off;   // W copy: reflectors and R (M x n, row-major)
+  int64_t v_off;   // full vectors (M x G x K)
+  int64_t xr_off;  // reduced regressors (Mr x n)
+  int64_t vr_off;  // reduced vectors (Mr x G x K)
+  int64_t tau_off; // reflector scalars (n)
+  int64_t t_off;   // block-reflector factors T (panels x 32 x 32)
+  int64_t om_off;  // Omega (G x G)
+};
+constexpr int RED_PANEL = 32;    // columns per Householder panel
+
 // Arguments of the two projection-pass kernels (host side).
 template <typename T>
 struct PassLaunch {
@@ -196,6 +214,14 @@ hipError_t launch_select_inner(const InstDesc* insts, int B, RhsState* st, const
                                int* inst_active, int want, hipStream_t s);
 hipError_t launch_update_c(const InstDesc* insts, int B, const RhsState* st,
                            const double* dwc, double* wc64, hipStream_t s);
+hipError_t launch_red_panel(const RedDesc* d, int B, int panel, double* W, double* tau,
+                           double* T, hipStream_t s);
+hipError_t launch_red_apply(const RedDesc* d, int B, int panel, const double* W,
+                           const double* T, double* C, int target_w, int trans, hipStream_t s);
+hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, const double* Yt,
+                             double* Xr, double* yr, hipStream_t s);
+hipError_t launch_red_tail(const RedDesc* d, int B, const double* Om, const double* Yt,
+                          const double* ur, double* u, int32_t* info, hipStream_t s);
 hipError_t launch_grad(const InstDesc* insts, const TileDesc* tiles, int ntiles, int B,
                        const int* colblk, const double* L, const double* U,
                        const double* beta, const double* lb, double* part, double* dOm,

@@ -1,0 +1,151 @@
+// Householder factorization of narrow blocks (at most 32 columns) by one
+// workgroup: shared by the per-block QR of the SUR regressors and the panel
+// steps of the model-reduction QR.
+#pragma once
+
+#include "glm_internal.h"
+
+#include <cmath>
+
+namespace glm {
+namespace {
+
+constexpr int QNT = 256;            // threads per QR workgroup
+// A subcolumn whose squared norm is below this is taken as exactly zero
+// (H = I).  Exact linear dependencies among the columns (the intercept of
+// every equation in W = [X_1 ... X_G]) leave subcolumns that shrink by about
+// eps per dependent column; squaring entries below ~1e-154 underflows and
+// would give a norm inconsistent with the stored reflector.
+constexpr double kQrTinyNorm2 = 1e-250;
+constexpr int QW = QNT / 64;        // waves per QR workgroup
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Factorization of blocks of at most 32 columns with the data mapping turned
+// around against the row-per-lane form: lane l owns column l % 32, and the row slot
+// 2 w + l / 32 of wave w takes rows slot, slot + 8, ...  A row segment is then
+// one coalesced access, QR_U rows per lane are in flight at once, the dot
+// products are one register per lane, and the pivot-column entry of a row
+// comes from its lane by a shuffle.  Arithmetic and order of the updates
+// follow k_qr; only the summation order of the dot products differs.
+constexpr int QR_U = 8;                  // rows in flight per lane
+constexpr int QR_SLOTS = QNT / 32;       // row slots per workgroup
+static_assert(((QR_SLOTS * QR_U) & (QR_SLOTS * QR_U - 1)) == 0, "rows per sweep step: a power of two");
+
+// value of column col in the row this lane's half-wave holds
+__device__ __forceinline__ double shfl_col(double v, int col) {
+  return __shfl(v, (int)(threadIdx.x & 32) | col, 64);
+}
+
+// dsum[k] = sum of dot over the workgroup's lanes of column k, k in [lo, cols)
+__device__ __forceinline__ void col_sum(double dot, int lo, int cols, double (*red)[QW],
+                                        double* dsum) {
+  const int tid = threadIdx.x;
+  dot += __shfl_xor(dot, 32, 64);
+  if ((tid & 63) < 32) red[tid & 31][tid >> 6] = dot;
+  __syncthreads();
+  if (tid >= lo && tid < cols) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < QW; ++q) s += red[tid][q];
+    dsum[tid] = s;
+  }
+  __syncthreads();
+}
+
+// Householder factorization of a rows x cols block (cols <= 32) at a0 with
+// row stride ld, in place (R on and above the diagonal, the reflectors below,
+// LAPACK geqr2 convention); tau_s receives the reflector scalars.  Called by
+// every thread of the workgroup.
+struct Qr32Shared {
+  double red[32][QW];
+  double dsum[32];
+  double pivrow[32];
+  double wk[32];
+  double tau_s[32];
+  double par[3];
+};
+
+__device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
+                            Qr32Shared& sh) {
+  double (*red)[QW] = sh.red;
+  double* dsum = sh.dsum;
+  double* pivrow = sh.pivrow;
+  double* wk = sh.wk;
+  double* tau_s = sh.tau_s;
+  double* par = sh.par;
+  const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
+  const bool colok = c < cols;
+  for (int p = 0; p <= cols; ++p) {
+    const int j = p - 1;
+    const double beta_j = (p > 0) ? par[0] : 0.0;
+    const double tau_j = (p > 0) ? par[1] : 0.0;
+    const double scale_j = (p > 0) ? par[2] : 0.0;
+    const double wkc = (p > 0 && c > j && colok) ? wk[c] : 0.0;
+    const int lo = (j > 0) ? j : 0;
+    double dot = 0.0;
+    // the sweep starts at a multiple of QR_SLOTS * QR_U, so that a row is
+    // loaded and stored by the same half-wave in every pass
+    for (int t0 = lo & ~(QR_SLOTS * QR_U - 1); t0 < rows; t0 += QR_SLOTS * QR_U) {
+      double a[QR_U];
+#pragma unroll
+      for (int u = 0; u < QR_U; ++u) {
+        const int t = t0 + slot + QR_SLOTS * u;
+        a[u] = (t < rows && t >= lo && colok && c >= lo) ? a0[(int64_t)t * ld + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < QR_U; ++u) {
+        const int t = t0 + slot + QR_SLOTS * u;
+        const bool rok = t < rows && t >= lo;
+        double x = a[u];
+        if (p > 0) {
+          const double aj = shfl_col(x, j);
+          const double vv = (t > j) ? aj * scale_j : 1.0;   // reflector j at row t
+          if (c > j) x -= tau_j * vv * wkc;
+          if (c == j) x = (t == j) ? beta_j : vv;
+          if (rok && colok && c >= j) a0[(int64_t)t * ld + c] = x;
+        }
+        if (p < cols) {
+          if (rok && t == p && colok && c >= p) pivrow[c] = x;
+          // dot products of the subcolumn below the pivot with every column
+          const double ap = shfl_col(x, p);
+          if (rok && t > p && c >= p) dot += ap * x;
+        }
+      }
+    }
+    if (p == cols) break;
+    __syncthreads();  // pivrow visible, all rows written
+    col_sum(dot, p, cols, red, dsum);
+    if (tid == 0) {
+      const double alpha = pivrow[p];
+      const double xnorm2 = dsum[p];            // squared norm below the pivot
+      const double nrm2 = alpha * alpha + xnorm2;
+      double beta, tau, scale;
+      if (!(xnorm2 > kQrTinyNorm2)) {
+        beta = alpha;  // H = I (LAPACK: tau = 0 when the subcolumn is zero)
+        tau = 0.0;
+        scale = 0.0;
+      } else {
+        const double nrm = sqrt(nrm2);
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      par[0] = beta;
+      par[1] = tau;
+      par[2] = scale;
+      tau_s[p] = tau;
+      for (int k = p + 1; k < cols; ++k)
+        wk[k] = pivrow[k] + scale * dsum[k];    // v^T a_k with v = [1; x * scale]
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+}
+
+}  // namespace
+}  // namespace glm

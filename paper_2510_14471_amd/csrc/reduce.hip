@@ -1,0 +1,286 @@
+// SUR model reduction (the remark on reducing the SUR model in the SUR
+// section): one Householder QR of W = [X_1 ... X_G] = Q [R; 0] per instance.
+// Rotating every equation by Q^T keeps Sigma = Omega (x) I_M, and the rotated
+// rows t >= n carry no information on beta, so the GLS of the first
+// Mr = min(M, n + 1) rotated rows is the GLS of the full model.  The full
+// residual-like vector is U = Q [U_red ; (Q^T Y)_{t >= Mr} Omega^-1].
+//
+// Q is kept as Householder panels of RED_PANEL columns in compact WY form,
+// Q = B_0 B_1 ... with B_p = I - V_p T_p V_p^T (T_p upper triangular):
+//   k_red_panel    factor panel p in place (reflectors below the diagonal),
+//                  store tau and T_p
+//   k_red_apply    C <- B_p^T C (the trailing columns of W while factoring,
+//                  and Y for Q^T Y) or C <- B_p C (Q Z for the residual)
+//   k_red_extract  reduced regressors (R rows) and reduced responses
+//   k_red_tail     U rows: the reduced solve's rows, then (Q^T Y) Omega^-1
+// One workgroup per instance in every kernel.
+#include "glm.h"
+#include "glm_internal.h"
+#include "qr_panel.h"
+
+#include <cmath>
+
+namespace glm {
+
+namespace {
+
+constexpr int RP = RED_PANEL;
+constexpr int RCH = 64;   // rows of V staged in LDS per chunk
+
+// V[r][j] of panel rows r (relative to the panel's first row): the unit
+// diagonal and zeros above it are implicit in the stored factorization.
+__device__ __forceinline__ double vpanel(const double* __restrict__ a0, int ld, int r, int j,
+                                         int rows, int w) {
+  if (j >= w || r >= rows) return 0.0;
+  if (r == j) return 1.0;
+  return r > j ? a0[(int64_t)r * ld + j] : 0.0;
+}
+
+__global__ void __launch_bounds__(QNT)
+k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W,
+            double* __restrict__ tau, double* __restrict__ T) {
+  const RedDesc d = descs[blockIdx.x];
+  const int c0 = panel * RP;
+  if (c0 >= d.kr) return;
+  const int w = min(RP, d.kr - c0), rows = d.M - c0, ld = d.n;
+  double* a0 = W + d.w_off + (int64_t)c0 * ld + c0;
+  __shared__ Qr32Shared sh;
+  __shared__ double S[RP][RP + 1];
+  __shared__ double part[QW][RP][RP];
+  qr32_factor(a0, rows, w, ld, sh);
+  const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
+  if (tid < w) tau[d.tau_off + c0 + tid] = sh.tau_s[tid];
+  // S = V^T V: lane c accumulates S[i][c] for every i over its rows
+  double acc[RP];
+#pragma unroll
+  for (int i = 0; i < RP; ++i) acc[i] = 0.0;
+  for (int r0 = 0; r0 < rows; r0 += QR_SLOTS) {
+    const int r = r0 + slot;
+    const double v = vpanel(a0, ld, r, c, rows, w);
+#pragma unroll
+    for (int i = 0; i < RP; ++i) acc[i] += shfl_col(v, i) * v;
+  }
+#pragma unroll
+  for (int i = 0; i < RP; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
+  if ((tid & 63) < 32)
+#pragma unroll
+    for (int i = 0; i < RP; ++i) part[tid >> 6][i][c] = acc[i];
+  __syncthreads();
+  for (int e = tid; e < RP * RP; e += QNT) {
+    const int i = e / RP, j = e % RP;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < QW; ++q) s += part[q][i][j];
+    S[i][j] = s;
+  }
+  __syncthreads();
+  // T (forward, columnwise): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j];
+  // built in LDS (the partial sums are no longer needed) by one thread
+  double (*Tl)[RP] = part[0];
+  for (int e = tid; e < RP * RP; e += QNT) Tl[e / RP][e % RP] = 0.0;
+  __syncthreads();
+  if (tid == 0)
+    for (int j = 0; j < w; ++j) {
+      const double tj = sh.tau_s[j];
+      for (int i = 0; i < j; ++i) {
+        double s = 0.0;
+        for (int k = i; k < j; ++k) s += Tl[i][k] * S[k][j];
+        Tl[i][j] = -tj * s;
+      }
+      Tl[j][j] = tj;
+    }
+  __syncthreads();
+  double* Tp = T + d.t_off + (int64_t)panel * RP * RP;
+  for (int e = tid; e < RP * RP; e += QNT) Tp[e] = Tl[e / RP][e % RP];
+}
+
+// C <- (I - V op(T) V^T) C on rows [c0, M) of one instance, op(T) = T^T when
+// trans (B_p^T) else T (B_p).  Target: the trailing columns of W (target_w)
+// or the M x (G K) vector array C.  Lane per column of C: z = V^T c, then
+// z' = op(T) z, then c -= V z', with V staged in LDS RCH rows at a time.
+__global__ void __launch_bounds__(QNT)
+k_red_apply(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
+            const double* __restrict__ T, double* __restrict__ C, int target_w, int trans) {
+  const RedDesc d = descs[blockIdx.x];
+  const int c0 = panel * RP;
+  if (c0 >= d.kr) return;
+  const int w = min(RP, d.kr - c0), rows = d.M - c0;
+  const double* a0 = W + d.w_off + (int64_t)c0 * d.n + c0;
+  int ncols, ld;
+  double* cb;
+  if (target_w) {
+    ncols = d.n - c0 - w;
+    ld = d.n;
+    cb = C + d.w_off + (int64_t)c0 * d.n + c0 + w;
+  } else {
+    ncols = d.G * d.K;
+    ld = ncols;
+    cb = C + d.v_off + (int64_t)c0 * ld;
+  }
+  if (ncols <= 0) return;
+  __shared__ double Ts[RP][RP + 1];
+  __shared__ double Vs[RCH][RP + 1];
+  const int tid = threadIdx.x;
+  {
+    const double* Tp = T + d.t_off + (int64_t)panel * RP * RP;
+    for (int e = tid; e < RP * RP; e += QNT) {
+      const int i = e / RP, j = e % RP;
+      Ts[i][j] = trans ? Tp[j * RP + i] : Tp[i * RP + j];
+    }
+  }
+  for (int col0 = 0; col0 < ncols; col0 += QNT) {
+    const int col = col0 + tid;
+    const bool ok = col < ncols;
+    double z[RP];
+#pragma unroll
+    for (int j = 0; j < RP; ++j) z[j] = 0.0;
+    for (int r0 = 0; r0 < rows; r0 += RCH) {
+      __syncthreads();
+      for (int e = tid; e < RCH * RP; e += QNT) {
+        const int r = e / RP, j = e % RP;
+        Vs[r][j] = vpanel(a0, d.n, r0 + r, j, rows, w);
+      }
+      __syncthreads();
+      const int nr = min(RCH, rows - r0);
+      for (int r = 0; r < nr; ++r) {
+        const double x = ok ? cb[(int64_t)(r0 + r) * ld + col] : 0.0;
+#pragma unroll
+        for (int j = 0; j < RP; ++j) z[j] += Vs[r][j] * x;
+      }
+    }
+    double zz[RP];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < RP; ++j) s += Ts[i][j] * z[j];
+      zz[i] = s;
+    }
+    for (int r0 = 0; r0 < rows; r0 += RCH) {
+      __syncthreads();
+      for (int e = tid; e < RCH * RP; e += QNT) {
+        const int r = e / RP, j = e % RP;
+        Vs[r][j] = vpanel(a0, d.n, r0 + r, j, rows, w);
+      }
+      __syncthreads();
+      const int nr = min(RCH, rows - r0);
+      if (ok)
+        for (int r = 0; r < nr; ++r) {
+          double* p = cb + (int64_t)(r0 + r) * ld + col;
+          double x = *p;
+#pragma unroll
+          for (int j = 0; j < RP; ++j) x -= Vs[r][j] * zz[j];
+          *p = x;
+        }
+    }
+  }
+}
+
+// Reduced regressors Xr[t][c] = R[t][c] (c >= t, t < kr; zero elsewhere) and
+// reduced responses yr = (Q^T Y) rows t < Mr.  Either output may be null.
+__global__ void __launch_bounds__(QNT)
+k_red_extract(const RedDesc* __restrict__ descs, const double* __restrict__ W,
+              const double* __restrict__ Yt, double* __restrict__ Xr, double* __restrict__ yr) {
+  const RedDesc d = descs[blockIdx.x];
+  if (Xr) {
+    const int64_t cnt = (int64_t)d.Mr * d.n;
+    for (int64_t e = threadIdx.x; e < cnt; e += QNT) {
+      const int t = (int)(e / d.n), c = (int)(e % d.n);
+      Xr[d.xr_off + e] = (t < d.kr && c >= t) ? W[d.w_off + e] : 0.0;
+    }
+  }
+  if (yr) {
+    const int64_t cnt = (int64_t)d.Mr * d.G * d.K;
+    for (int64_t e = threadIdx.x; e < cnt; e += QNT) yr[d.vr_off + e] = Yt[d.v_off + e];
+  }
+}
+
+// U before the final rotation: rows t < Mr from the reduced solve, rows
+// t >= Mr = (Q^T Y)[t] Omega^-1 (row by row, every rhs).  Omega^-1 by
+// Gauss-Jordan elimination without pivoting (Omega symmetric positive
+// definite); a non-positive pivot marks every rhs of the instance as a
+// breakdown and leaves zeros in those rows.
+__global__ void __launch_bounds__(QNT)
+k_red_tail(const RedDesc* __restrict__ descs, const double* __restrict__ Om,
+           const double* __restrict__ Yt, const double* __restrict__ ur,
+           double* __restrict__ u, int32_t* __restrict__ info) {
+  const RedDesc d = descs[blockIdx.x];
+  const int G = d.G, K = d.K, P = G * K, tid = threadIdx.x;
+  __shared__ double A[64][129];   // [Omega | I] -> [I | Omega^-1], G <= 64
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  for (int e = tid; e < G * 2 * G; e += QNT) {
+    const int i = e / (2 * G), j = e % (2 * G);
+    A[i][j] = (j < G) ? Om[d.om_off + (int64_t)i * G + j] : (j - G == i ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  double scale = 0.0;
+  for (int i = 0; i < G; ++i) scale = fmax(scale, fabs(A[i][i]));
+  for (int p = 0; p < G; ++p) {
+    const double piv = A[p][p];
+    __syncthreads();
+    if (!(piv > 1e-14 * scale)) {
+      if (tid == 0) s_bad = 1;
+      break;
+    }
+    // row p scaled, then eliminated from every other row
+    for (int j = tid; j < 2 * G; j += QNT) A[p][j] /= piv;
+    __syncthreads();
+    // column p is left alone here (it is the multiplier every update reads)
+    for (int e = tid; e < G * 2 * G; e += QNT) {
+      const int i = e / (2 * G), j = e % (2 * G);
+      if (i != p && j != p) A[i][j] -= A[i][p] * A[p][j];
+    }
+    __syncthreads();
+    for (int i = tid; i < G; i += QNT)
+      if (i != p) A[i][p] = 0.0;
+    __syncthreads();
+  }
+  __syncthreads();
+  const bool bad = s_bad != 0;
+  if (bad && info && tid < K) info[d.rhs0 + tid] = GLM_INFO_BREAKDOWN;
+  const int64_t head = (int64_t)d.Mr * P, all = (int64_t)d.M * P;
+  for (int64_t e = tid; e < head; e += QNT) u[d.v_off + e] = ur[d.vr_off + e];
+  for (int64_t e = head + tid; e < all; e += QNT) {
+    const int64_t t = e / P;
+    const int rem = (int)(e - t * P), j = rem / K, k = rem - (rem / K) * K;
+    double s = 0.0;
+    if (!bad) {
+      const double* yrow = Yt + d.v_off + t * P + k;
+      for (int i = 0; i < G; ++i) s += yrow[(int64_t)i * K] * A[i][G + j];
+    }
+    u[d.v_off + e] = s;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_red_panel(const RedDesc* d, int B, int panel, double* W, double* tau,
+                           double* T, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_red_panel, dim3(B), dim3(QNT), 0, s, d, panel, W, tau, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_red_apply(const RedDesc* d, int B, int panel, const double* W,
+                           const double* T, double* C, int target_w, int trans, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_red_apply, dim3(B), dim3(QNT), 0, s, d, panel, W, T, C, target_w, trans);
+  return hipGetLastError();
+}
+
+hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, const double* Yt,
+                             double* Xr, double* yr, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_red_extract, dim3(B), dim3(QNT), 0, s, d, W, Yt, Xr, yr);
+  return hipGetLastError();
+}
+
+hipError_t launch_red_tail(const RedDesc* d, int B, const double* Om, const double* Yt,
+                          const double* ur, double* u, int32_t* info, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_red_tail, dim3(B), dim3(QNT), 0, s, d, Om, Yt, ur, u, info);
+  return hipGetLastError();
+}
+
+}  // namespace glm

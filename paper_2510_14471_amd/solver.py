@@ -105,9 +105,15 @@ def unpack(lay: BatchLayout, flat, kind: str):
 class SURSolver:
     """Owns one workspace and one factor handle for a fixed batch shape."""
 
-    def __init__(self, layout: BatchLayout, precision: str = "fp64", device="cuda:0"):
+    def __init__(self, layout: BatchLayout, precision: str = "fp64", device="cuda:0",
+                 reduce: bool = False):
+        """reduce: solve through the SUR model reduction (one QR of
+        W = [X_1 ... X_G] per instance; the iteration runs on min(M, n + 1)
+        rotated observations).  Forward solves only: backward() and factors()
+        raise on such a solver."""
         self.layout = layout
-        self.precision = _lib.PRECISIONS[precision]
+        self.reduce = bool(reduce)
+        self.precision = _lib.PRECISIONS[precision] | (_lib.GLM_REDUCED if reduce else 0)
         self.device = torch.device(device)
         self._shape = layout.shape()
         rc = _lib.glm_validate_shape(self._shape)

@@ -119,3 +119,31 @@ def test_workspace_for_the_batched_workload_fits_one_gpu():
     for prec in (_lib.GLM_FP64, _lib.GLM_MIXED):
         nb = _lib.glm_workspace_bytes(lay.shape(), prec)
         assert 0 < nb < 40e9
+
+
+def test_reduced_workspace_and_flag_checks():
+    """GLM_REDUCED sizes its own workspace (the W copy and rotated vectors plus
+    the reduced problem's workspace, smaller than the full problem's), rejects
+    an unknown base precision, and checks the workspace before device work."""
+    import ctypes
+    from paper_2510_14471_amd import _lib
+    s = _shape([3, 5], [900, 400], [16, 16], [4, 6, 5, 3, 3, 2, 7, 4])
+    for base in (_lib.GLM_FP64, _lib.GLM_MIXED):
+        full = _lib.glm_workspace_bytes(s, base)
+        red = _lib.glm_workspace_bytes(s, base | _lib.GLM_REDUCED)
+        assert 0 < red and 0 < full
+    assert _lib.glm_workspace_bytes(s, 2 | _lib.GLM_REDUCED) == 0
+    bad = _shape([3], [10], [1], [4, 6, 11])                 # n_i > M
+    assert _lib.glm_workspace_bytes(bad, _lib.GLM_FP64 | _lib.GLM_REDUCED) == 0
+    need = _lib.glm_workspace_bytes(s, _lib.GLM_MIXED | _lib.GLM_REDUCED)
+    out = ctypes.c_void_p()
+    rc = _lib._lib.glm_qr_factor(s.ptr(), _lib.GLM_MIXED | _lib.GLM_REDUCED, ctypes.c_void_p(8),
+                                 None, ctypes.c_void_p(8), need - 1, None, ctypes.byref(out))
+    assert rc == _lib.GLM_EWORKSPACE and not out.value
+
+
+def test_reduction_needs_at_most_64_equations():
+    from paper_2510_14471_amd import _lib
+    s = _shape([65], [200], [1], [1] * 65)
+    assert _lib.glm_workspace_bytes(s, _lib.GLM_FP64) > 0
+    assert _lib.glm_workspace_bytes(s, _lib.GLM_FP64 | _lib.GLM_REDUCED) == 0
