@@ -414,13 +414,13 @@ namespace {
 // equations and blocks with min(M, n + 1) observations) and the layout of
 // the reduction buffers, followed by the reduced problem's own workspace.
 struct RedPlan {
-  int B = 0, maxpan = 0;
+  int B = 0, maxpan = 0, maxn = 0, maxGK = 0, maxM = 0;
   std::vector<RedDesc> d;
   std::vector<int32_t> G, M, K, k, n;
   glm_shape sub{};
-  int64_t sumMn = 0, sumMGK = 0, sumMrn = 0, sumMrGK = 0, sumn = 0, sumT = 0;
+  int64_t sumMn = 0, sumMGK = 0, sumMrn = 0, sumMrGK = 0, sumn = 0, sumT = 0, sumG2 = 0;
   size_t o_desc = 0, o_W = 0, o_tau = 0, o_T = 0, o_Yt = 0, o_Xr = 0, o_yr = 0, o_ur = 0,
-         o_sub = 0, sub_bytes = 0, total = 0;
+         o_Oinv = 0, o_sub = 0, sub_bytes = 0, total = 0;
 };
 
 int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
@@ -451,6 +451,9 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     d.om_off = om;
     const int npan = (d.kr + RED_PANEL - 1) / RED_PANEL;
     r.maxpan = std::max(r.maxpan, npan);
+    r.maxn = std::max(r.maxn, n);
+    r.maxGK = std::max(r.maxGK, d.G * d.K);
+    r.maxM = std::max(r.maxM, d.M);
     r.sumMn += (int64_t)d.M * n;
     r.sumMGK += (int64_t)d.M * d.G * d.K;
     r.sumMrn += (int64_t)d.Mr * n;
@@ -458,6 +461,7 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     r.sumn += n;
     r.sumT += (int64_t)npan * RED_PANEL * RED_PANEL;
     om += (int64_t)d.G * d.G;
+    r.sumG2 = om;
     rhs += d.K;
     r.d.push_back(d);
     r.G.push_back(d.G);
@@ -493,6 +497,7 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
   r.o_Xr = take(8 * r.sumMrn);
   r.o_yr = take(8 * r.sumMrGK);
   r.o_ur = take(8 * r.sumMrGK);
+  r.o_Oinv = take(8 * r.sumG2);
   r.o_sub = take(r.sub_bytes);
   r.total = o;
   return GLM_OK;
@@ -960,7 +965,7 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
   if (!e) e = hipMemcpyAsync(W, X, 8 * r.sumMn, hipMemcpyDeviceToDevice, stream);
   for (int p = 0; p < r.maxpan && !e; ++p) {
     e = launch_red_panel(dd, r.B, p, W, f->at<double>(r.o_tau), T, stream);
-    if (!e) e = launch_red_apply(dd, r.B, p, W, T, W, 1, 1, stream);
+    if (!e) e = launch_red_apply(dd, r.B, p, W, T, W, 1, 1, r.maxn - p * RED_PANEL, stream);
   }
   if (!e) e = launch_red_extract(dd, r.B, W, nullptr, f->at<double>(r.o_Xr), nullptr, stream);
   if (e != hipSuccess) {
@@ -990,14 +995,15 @@ int solve_reduced(glm_factor* f, const double* Omega, const double* y, const dou
   double* ur = f->at<double>(rp.o_ur);
   GLM_CHECK(hipMemcpyAsync(Yt, y, 8 * rp.sumMGK, hipMemcpyDeviceToDevice, stream));
   for (int p = 0; p < rp.maxpan; ++p)
-    GLM_CHECK(launch_red_apply(dd, rp.B, p, W, T, Yt, 0, 1, stream));
+    GLM_CHECK(launch_red_apply(dd, rp.B, p, W, T, Yt, 0, 1, rp.maxGK, stream));
   GLM_CHECK(launch_red_extract(dd, rp.B, W, Yt, nullptr, f->at<double>(rp.o_yr), stream));
   int rc = glm_gls_solve(f->sub, Omega, f->at<double>(rp.o_yr), r, tol, max_iter, beta, ur, uc,
                          info, iters, stream);
   if (rc != GLM_OK) return rc;
-  GLM_CHECK(launch_red_tail(dd, rp.B, Omega, Yt, ur, u, info, stream));
+  GLM_CHECK(launch_red_tail(dd, rp.B, rp.maxM, Omega, f->at<double>(rp.o_Oinv), Yt, ur, u, info,
+                            stream));
   for (int p = rp.maxpan - 1; p >= 0; --p)
-    GLM_CHECK(launch_red_apply(dd, rp.B, p, W, T, u, 0, 0, stream));
+    GLM_CHECK(launch_red_apply(dd, rp.B, p, W, T, u, 0, 0, rp.maxGK, stream));
   f->stats = f->sub->stats;
   f->stats.launches += 2 * rp.maxpan + 2;
   return GLM_OK;

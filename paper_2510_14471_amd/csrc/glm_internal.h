@@ -217,11 +217,13 @@ hipError_t launch_update_c(const InstDesc* insts, int B, const RhsState* st,
 hipError_t launch_red_panel(const RedDesc* d, int B, int panel, double* W, double* tau,
                            double* T, hipStream_t s);
 hipError_t launch_red_apply(const RedDesc* d, int B, int panel, const double* W,
-                           const double* T, double* C, int target_w, int trans, hipStream_t s);
+                           const double* T, double* C, int target_w, int trans, int maxcols,
+                           hipStream_t s);
 hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, const double* Yt,
                              double* Xr, double* yr, hipStream_t s);
-hipError_t launch_red_tail(const RedDesc* d, int B, const double* Om, const double* Yt,
-                          const double* ur, double* u, int32_t* info, hipStream_t s);
+hipError_t launch_red_tail(const RedDesc* d, int B, int maxM, const double* Om, double* Oinv,
+                          const double* Yt, const double* ur, double* u, int32_t* info,
+                          hipStream_t s);
 hipError_t launch_grad(const InstDesc* insts, const TileDesc* tiles, int ntiles, int B,
                        const int* colblk, const double* L, const double* U,
                        const double* beta, const double* lb, double* part, double* dOm,

@@ -32,7 +32,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // products are one register per lane, and the pivot-column entry of a row
 // comes from its lane by a shuffle.  Arithmetic and order of the updates
 // follow k_qr; only the summation order of the dot products differs.
-constexpr int QR_U = 8;                  // rows in flight per lane
+constexpr int QR_U = 32;                 // rows in flight per lane
 constexpr int QR_SLOTS = QNT / 32;       // row slots per workgroup
 static_assert(((QR_SLOTS * QR_U) & (QR_SLOTS * QR_U - 1)) == 0, "rows per sweep step: a power of two");
 

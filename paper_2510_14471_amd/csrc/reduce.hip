@@ -12,8 +12,9 @@
 //   k_red_apply    C <- B_p^T C (the trailing columns of W while factoring,
 //                  and Y for Q^T Y) or C <- B_p C (Q Z for the residual)
 //   k_red_extract  reduced regressors (R rows) and reduced responses
+//   k_red_oinv     Omega^-1 per instance
 //   k_red_tail     U rows: the reduced solve's rows, then (Q^T Y) Omega^-1
-// One workgroup per instance in every kernel.
+// One workgroup per instance, or per (instance, chunk of columns or rows).
 #include "glm.h"
 #include "glm_internal.h"
 #include "qr_panel.h"
@@ -54,11 +55,16 @@ k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
   double acc[RP];
 #pragma unroll
   for (int i = 0; i < RP; ++i) acc[i] = 0.0;
-  for (int r0 = 0; r0 < rows; r0 += QR_SLOTS) {
-    const int r = r0 + slot;
-    const double v = vpanel(a0, ld, r, c, rows, w);
+  // rows r0 + slot + QR_SLOTS q: the same half-wave that factored them
+  constexpr int SU = 4;
+  for (int r0 = 0; r0 < rows; r0 += QR_SLOTS * SU) {
+    double v[SU];
 #pragma unroll
-    for (int i = 0; i < RP; ++i) acc[i] += shfl_col(v, i) * v;
+    for (int q = 0; q < SU; ++q) v[q] = vpanel(a0, ld, r0 + slot + QR_SLOTS * q, c, rows, w);
+#pragma unroll
+    for (int q = 0; q < SU; ++q)
+#pragma unroll
+      for (int i = 0; i < RP; ++i) acc[i] += shfl_col(v[q], i) * v[q];
   }
 #pragma unroll
   for (int i = 0; i < RP; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
@@ -96,8 +102,12 @@ k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
 
 // C <- (I - V op(T) V^T) C on rows [c0, M) of one instance, op(T) = T^T when
 // trans (B_p^T) else T (B_p).  Target: the trailing columns of W (target_w)
-// or the M x (G K) vector array C.  Lane per column of C: z = V^T c, then
-// z' = op(T) z, then c -= V z', with V staged in LDS RCH rows at a time.
+// or the M x (G K) vector array C.  Workgroup (instance, chunk of QNT
+// columns), lane per column: z = V^T c, then z' = op(T) z, then c -= V z',
+// with V staged in LDS RCH rows at a time and RU rows of c loaded before
+// they are used.
+constexpr int RU = 8;
+
 __global__ void __launch_bounds__(QNT)
 k_red_apply(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
             const double* __restrict__ T, double* __restrict__ C, int target_w, int trans) {
@@ -117,7 +127,8 @@ k_red_apply(const RedDesc* __restrict__ descs, int panel, const double* __restri
     ld = ncols;
     cb = C + d.v_off + (int64_t)c0 * ld;
   }
-  if (ncols <= 0) return;
+  const int col0 = blockIdx.y * QNT;
+  if (col0 >= ncols) return;
   __shared__ double Ts[RP][RP + 1];
   __shared__ double Vs[RCH][RP + 1];
   const int tid = threadIdx.x;
@@ -128,51 +139,61 @@ k_red_apply(const RedDesc* __restrict__ descs, int panel, const double* __restri
       Ts[i][j] = trans ? Tp[j * RP + i] : Tp[i * RP + j];
     }
   }
-  for (int col0 = 0; col0 < ncols; col0 += QNT) {
-    const int col = col0 + tid;
-    const bool ok = col < ncols;
-    double z[RP];
+  const int col = col0 + tid;
+  const bool ok = col < ncols;
+  double* cc = cb + col;
+  double z[RP];
 #pragma unroll
-    for (int j = 0; j < RP; ++j) z[j] = 0.0;
-    for (int r0 = 0; r0 < rows; r0 += RCH) {
-      __syncthreads();
-      for (int e = tid; e < RCH * RP; e += QNT) {
-        const int r = e / RP, j = e % RP;
-        Vs[r][j] = vpanel(a0, d.n, r0 + r, j, rows, w);
-      }
-      __syncthreads();
-      const int nr = min(RCH, rows - r0);
-      for (int r = 0; r < nr; ++r) {
-        const double x = ok ? cb[(int64_t)(r0 + r) * ld + col] : 0.0;
-#pragma unroll
-        for (int j = 0; j < RP; ++j) z[j] += Vs[r][j] * x;
-      }
+  for (int j = 0; j < RP; ++j) z[j] = 0.0;
+  for (int r0 = 0; r0 < rows; r0 += RCH) {
+    __syncthreads();
+    for (int e = tid; e < RCH * RP; e += QNT) {
+      const int r = e / RP, j = e % RP;
+      Vs[r][j] = vpanel(a0, d.n, r0 + r, j, rows, w);
     }
-    double zz[RP];
+    __syncthreads();
+    const int nr = min(RCH, rows - r0);
+    for (int r = 0; r < nr; r += RU) {
+      double x[RU];
 #pragma unroll
-    for (int i = 0; i < RP; ++i) {
-      double s = 0.0;
+      for (int q = 0; q < RU; ++q)
+        x[q] = (ok && r + q < nr) ? cc[(int64_t)(r0 + r + q) * ld] : 0.0;
 #pragma unroll
-      for (int j = 0; j < RP; ++j) s += Ts[i][j] * z[j];
-      zz[i] = s;
+      for (int q = 0; q < RU; ++q)
+#pragma unroll
+        for (int j = 0; j < RP; ++j) z[j] += Vs[r + q][j] * x[q];
     }
-    for (int r0 = 0; r0 < rows; r0 += RCH) {
-      __syncthreads();
-      for (int e = tid; e < RCH * RP; e += QNT) {
-        const int r = e / RP, j = e % RP;
-        Vs[r][j] = vpanel(a0, d.n, r0 + r, j, rows, w);
-      }
-      __syncthreads();
-      const int nr = min(RCH, rows - r0);
-      if (ok)
-        for (int r = 0; r < nr; ++r) {
-          double* p = cb + (int64_t)(r0 + r) * ld + col;
-          double x = *p;
+  }
+  double zz[RP];
 #pragma unroll
-          for (int j = 0; j < RP; ++j) x -= Vs[r][j] * zz[j];
-          *p = x;
+  for (int i = 0; i < RP; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < RP; ++j) s += Ts[i][j] * z[j];
+    zz[i] = s;
+  }
+  for (int r0 = 0; r0 < rows; r0 += RCH) {
+    __syncthreads();
+    for (int e = tid; e < RCH * RP; e += QNT) {
+      const int r = e / RP, j = e % RP;
+      Vs[r][j] = vpanel(a0, d.n, r0 + r, j, rows, w);
+    }
+    __syncthreads();
+    const int nr = min(RCH, rows - r0);
+    if (ok)
+      for (int r = 0; r < nr; r += RU) {
+        double x[RU];
+#pragma unroll
+        for (int q = 0; q < RU; ++q)
+          x[q] = (r + q < nr) ? cc[(int64_t)(r0 + r + q) * ld] : 0.0;
+#pragma unroll
+        for (int q = 0; q < RU; ++q) {
+          double v = x[q];
+#pragma unroll
+          for (int j = 0; j < RP; ++j) v -= Vs[r + q][j] * zz[j];
+          if (r + q < nr) cc[(int64_t)(r0 + r + q) * ld] = v;
         }
-    }
+      }
   }
 }
 
@@ -195,17 +216,14 @@ k_red_extract(const RedDesc* __restrict__ descs, const double* __restrict__ W,
   }
 }
 
-// U before the final rotation: rows t < Mr from the reduced solve, rows
-// t >= Mr = (Q^T Y)[t] Omega^-1 (row by row, every rhs).  Omega^-1 by
-// Gauss-Jordan elimination without pivoting (Omega symmetric positive
-// definite); a non-positive pivot marks every rhs of the instance as a
-// breakdown and leaves zeros in those rows.
+// Omega^-1 of every instance by Gauss-Jordan elimination without pivoting
+// (Omega symmetric positive definite); a non-positive pivot marks every rhs of
+// the instance as a breakdown and leaves a zero inverse.
 __global__ void __launch_bounds__(QNT)
-k_red_tail(const RedDesc* __restrict__ descs, const double* __restrict__ Om,
-           const double* __restrict__ Yt, const double* __restrict__ ur,
-           double* __restrict__ u, int32_t* __restrict__ info) {
+k_red_oinv(const RedDesc* __restrict__ descs, const double* __restrict__ Om,
+           double* __restrict__ Oinv, int32_t* __restrict__ info) {
   const RedDesc d = descs[blockIdx.x];
-  const int G = d.G, K = d.K, P = G * K, tid = threadIdx.x;
+  const int G = d.G, tid = threadIdx.x;
   __shared__ double A[64][129];   // [Omega | I] -> [I | Omega^-1], G <= 64
   __shared__ int s_bad;
   if (tid == 0) s_bad = 0;
@@ -223,10 +241,10 @@ k_red_tail(const RedDesc* __restrict__ descs, const double* __restrict__ Om,
       if (tid == 0) s_bad = 1;
       break;
     }
-    // row p scaled, then eliminated from every other row
+    // row p scaled, then eliminated from every other row; column p is left
+    // alone here (it is the multiplier every update reads)
     for (int j = tid; j < 2 * G; j += QNT) A[p][j] /= piv;
     __syncthreads();
-    // column p is left alone here (it is the multiplier every update reads)
     for (int e = tid; e < G * 2 * G; e += QNT) {
       const int i = e / (2 * G), j = e % (2 * G);
       if (i != p && j != p) A[i][j] -= A[i][p] * A[p][j];
@@ -238,18 +256,39 @@ k_red_tail(const RedDesc* __restrict__ descs, const double* __restrict__ Om,
   }
   __syncthreads();
   const bool bad = s_bad != 0;
-  if (bad && info && tid < K) info[d.rhs0 + tid] = GLM_INFO_BREAKDOWN;
-  const int64_t head = (int64_t)d.Mr * P, all = (int64_t)d.M * P;
-  for (int64_t e = tid; e < head; e += QNT) u[d.v_off + e] = ur[d.vr_off + e];
-  for (int64_t e = head + tid; e < all; e += QNT) {
+  if (bad && info && tid < d.K) info[d.rhs0 + tid] = GLM_INFO_BREAKDOWN;
+  for (int e = tid; e < G * G; e += QNT)
+    Oinv[d.om_off + e] = bad ? 0.0 : A[e / G][G + e % G];
+}
+
+// U before the final rotation, RTR rows per workgroup (instance, chunk):
+// rows t < Mr from the reduced solve, rows t >= Mr = (Q^T Y)[t] Omega^-1.
+constexpr int RTR = 64;
+
+__global__ void __launch_bounds__(QNT)
+k_red_tail(const RedDesc* __restrict__ descs, const double* __restrict__ Oinv,
+           const double* __restrict__ Yt, const double* __restrict__ ur,
+           double* __restrict__ u) {
+  const RedDesc d = descs[blockIdx.x];
+  const int t0 = blockIdx.y * RTR;
+  if (t0 >= d.M) return;
+  const int G = d.G, K = d.K, P = G * K, tid = threadIdx.x;
+  const int t1 = min(d.M, t0 + RTR);
+  __shared__ double Oi[64 * 64];
+  if (t1 > d.Mr)
+    for (int e = tid; e < G * G; e += QNT) Oi[e] = Oinv[d.om_off + e];
+  __syncthreads();
+  for (int64_t e = (int64_t)t0 * P + tid; e < (int64_t)t1 * P; e += QNT) {
     const int64_t t = e / P;
-    const int rem = (int)(e - t * P), j = rem / K, k = rem - (rem / K) * K;
-    double s = 0.0;
-    if (!bad) {
+    if (t < d.Mr) {
+      u[d.v_off + e] = ur[d.vr_off + e];
+    } else {
+      const int rem = (int)(e - t * P), j = rem / K, k = rem - (rem / K) * K;
       const double* yrow = Yt + d.v_off + t * P + k;
-      for (int i = 0; i < G; ++i) s += yrow[(int64_t)i * K] * A[i][G + j];
+      double s = 0.0;
+      for (int i = 0; i < G; ++i) s += yrow[(int64_t)i * K] * Oi[i * G + j];
+      u[d.v_off + e] = s;
     }
-    u[d.v_off + e] = s;
   }
 }
 
@@ -263,9 +302,12 @@ hipError_t launch_red_panel(const RedDesc* d, int B, int panel, double* W, doubl
 }
 
 hipError_t launch_red_apply(const RedDesc* d, int B, int panel, const double* W,
-                           const double* T, double* C, int target_w, int trans, hipStream_t s) {
-  if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_red_apply, dim3(B), dim3(QNT), 0, s, d, panel, W, T, C, target_w, trans);
+                           const double* T, double* C, int target_w, int trans, int maxcols,
+                           hipStream_t s) {
+  if (B <= 0 || maxcols <= 0) return hipSuccess;
+  const int chunks = (maxcols + QNT - 1) / QNT;
+  hipLaunchKernelGGL(k_red_apply, dim3(B, chunks), dim3(QNT), 0, s, d, panel, W, T, C,
+                     target_w, trans);
   return hipGetLastError();
 }
 
@@ -276,10 +318,14 @@ hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, const do
   return hipGetLastError();
 }
 
-hipError_t launch_red_tail(const RedDesc* d, int B, const double* Om, const double* Yt,
-                          const double* ur, double* u, int32_t* info, hipStream_t s) {
+hipError_t launch_red_tail(const RedDesc* d, int B, int maxM, const double* Om, double* Oinv,
+                          const double* Yt, const double* ur, double* u, int32_t* info,
+                          hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_red_tail, dim3(B), dim3(QNT), 0, s, d, Om, Yt, ur, u, info);
+  hipLaunchKernelGGL(k_red_oinv, dim3(B), dim3(QNT), 0, s, d, Om, Oinv, info);
+  if (hipError_t e = hipGetLastError()) return e;
+  const int chunks = (maxM + RTR - 1) / RTR;
+  hipLaunchKernelGGL(k_red_tail, dim3(B, chunks), dim3(QNT), 0, s, d, Oinv, Yt, ur, u);
   return hipGetLastError();
 }
 
