@@ -29,9 +29,12 @@ HBM_PEAK_GBS = 8000.0
 # for the kernel sources it was taken from
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_proj_sur_batch512_k16.json")
 KERNEL_SOURCES = ["paper_2510_14471_amd/csrc/proj.hip", "paper_2510_14471_amd/csrc/api.hip",
-                  "paper_2510_14471_amd/csrc/glm_internal.h"]
+                  "paper_2510_14471_amd/csrc/glm_internal.h", "paper_2510_14471_amd/csrc/reduce.hip",
+                  "paper_2510_14471_amd/csrc/qr_panel.h"]
 PASS_NAMES = {0: "k_proj_a<float> (pass A: u <- g + mu u, B = U Omega, d = u.B, T += Q^T B)",
-              1: "k_proj_b<float> (pass B: g -= (lambda/alpha)(B - Q T), w -= lambda u, c = g.g)"}
+              1: "k_proj_b<float> (pass B: g -= (lambda/alpha)(B - Q T), w -= lambda u, c = g.g)",
+              2: "k_red_apply (model reduction: C <- (I - V T' V^T) C, block reflector of a "
+                 "32-column Householder panel of W = [X_1 ... X_G], on W, Y and U)"}
 
 
 def log(msg):
@@ -55,6 +58,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-unreduced", action="store_true",
+                    help="skip the runs without the model reduction")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -97,23 +102,32 @@ def main():
         dt = time.perf_counter() - t
         prof = None
         if profile:
-            prof = {k: solver.profile_read(k) for k in (0, 1)}
+            prof = {k: solver.profile_read(k) for k in PASS_NAMES}
             solver.profile(False)
         return dt, iters, outer, beta, u, info, prof
 
+    # the product path (model reduction: one QR of W, the iteration on n + 1
+    # rotated rows) and the iteration on all M rows, each in mixed precision
+    # and in plain FP64
+    runs = [("mixed", True), ("fp64", True)]
+    if not args.no_unreduced:
+        runs += [("mixed", False), ("fp64", False)]
+    if args.no_fp64:
+        runs = [r for r in runs if r[0] == "mixed"]
     results = {}
-    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
-        s = glm.SURSolver(lay, prec)
-        log(f"{prec}: workspace {s.workspace_bytes / 1e9:.2f} GB")
+    for prec, red in runs:
+        key = prec + ("" if red else "_unreduced")
+        s = glm.SURSolver(lay, prec, reduce=red)
+        log(f"{key}: workspace {s.workspace_bytes / 1e9:.2f} GB")
         for _ in range(args.warmup):
             timed(s, 1)
         dt, iters, outer, beta, u, info, prof = timed(s, args.steps, profile=(prec == "mixed"))
         infos = info.cpu().numpy()
-        results[prec] = dict(dt=dt, iters=iters, outer=outer, beta=beta, u=u,
-                             ok=int(np.sum((infos == 0) | (infos == 1))), prof=prof)
-        log(f"{prec}: {args.steps} steps in {dt:.3f}s -> {n_solves * args.steps / dt:.1f} solves/s,"
+        results[key] = dict(dt=dt, iters=iters, outer=outer, beta=beta, u=u,
+                            ok=int(np.sum((infos == 0) | (infos == 1))), prof=prof)
+        log(f"{key}: {args.steps} steps in {dt:.3f}s -> {n_solves * args.steps / dt:.1f} solves/s,"
             f" {iters / args.steps:.0f} PCG iterations/step, outer {outer / args.steps:.1f},"
-            f" ok {results[prec]['ok']}/{n_solves}")
+            f" ok {results[key]['ok']}/{n_solves}")
         s.close()
         del s
         torch.cuda.empty_cache()
@@ -122,12 +136,13 @@ def main():
     from oracle import gls as ogls
     errs = {}
     sample = list(range(0, len(insts), max(1, len(insts) // max(1, args.check))))[: args.check]
+    ref = {b: ogls.sur_gls(insts[b]) for b in sample}
     for prec, r in results.items():
         betas = glm.unpack(lay, r["beta"], "beta")
         us = glm.unpack(lay, r["u"], "u")
         eb = eu = 0.0
         for b in sample:
-            beta_o, U_o = ogls.sur_gls(insts[b])
+            beta_o, U_o = ref[b]
             for k in range(insts[b].K):
                 eb = max(eb, rel(betas[b][:, k], beta_o[:, k]))
                 eu = max(eu, rel(us[b][:, :, k], U_o[:, :, k]))
@@ -150,8 +165,9 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"sur_batch{len(insts)}_K16: G~U{{4..32}}, M~U{{500..5000}}, "
-                               "n_i~U{3..20}, Omega=AA^T+0.1I; step = QR factor + mixed "
-                               "solve of all (instance, rhs)",
+                               "n_i~U{3..20}, Omega=AA^T+0.1I; step = model reduction (QR of "
+                               "W = [X_1..X_G], rotation of Y) + per-block QR + solve of all "
+                               "(instance, rhs), u of the full model",
                    "instances": len(insts), "solves_per_step": n_solves, "tol": args.tol},
         "pcg_iterations_per_s": round(mixed["iters"] / mixed["dt"], 1),
         "outer_steps": round(mixed["outer"] / args.steps, 2),
@@ -164,23 +180,22 @@ def main():
         out["fp64_solves_per_s"] = round(v64, 2)
         out["speedup_mixed_vs_fp64"] = round(value / v64, 3)
         out["fp64_pcg_iterations_per_s"] = round(f64["iters"] / f64["dt"], 1)
-    prof = mixed["prof"]
-    if prof:
-        kid = max((0, 1), key=lambda k: prof[k][1])
-        n_l, ms, by = prof[kid]
-        names = PASS_NAMES
-        ach = (by / n_l) / (ms / n_l * 1e-3) / 1e9 if n_l and ms > 0 else 0.0
-        out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                           "traffic": measured_traffic(kid), "kernel": names[kid],
-                           "launches": n_l,
-                           "avg_us": round(1000 * ms / max(n_l, 1), 2),
-                           "alg_bytes_per_launch": round(by / max(n_l, 1))}
-        other = 1 - kid
-        n2, ms2, by2 = prof[other]
-        if n2:
-            out["roofline_other"] = {"kernel": names[other], "avg_us": round(1000 * ms2 / n2, 2),
-                                     "achieved": round((by2 / n2) / (ms2 / n2 * 1e-3) / 1e9, 1)}
+    if "mixed_unreduced" in results:
+        un = {"mixed_solves_per_s": round(n_solves * args.steps / results["mixed_unreduced"]["dt"], 2),
+              "pcg_iterations_per_s": round(results["mixed_unreduced"]["iters"] /
+                                            results["mixed_unreduced"]["dt"], 1)}
+        if "fp64_unreduced" in results:
+            un["fp64_solves_per_s"] = round(n_solves * args.steps / results["fp64_unreduced"]["dt"], 2)
+            un["speedup_mixed_vs_fp64"] = round(un["mixed_solves_per_s"] / un["fp64_solves_per_s"], 3)
+        rl = roofline(results["mixed_unreduced"]["prof"], reduced=False)
+        if rl:
+            un["roofline"] = rl[0]
+        out["without_model_reduction"] = un
+    rl = roofline(mixed["prof"], reduced=True)
+    if rl:
+        out["roofline"], others = rl
+        if others:
+            out["roofline_other"] = others
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -195,8 +210,8 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(pass_id):
-    """HBM bytes per launch of the timed pass from the committed counter
+def measured_traffic(pass_id, reduced):
+    """HBM bytes per launch of the timed kernel from the committed counter
     summary, or None when it is missing or the kernel sources changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -205,8 +220,34 @@ def measured_traffic(pass_id):
         return None
     if t.get("sources_sha256") != kernel_sources_sha256():
         return None
-    k = t.get("passes", {}).get(str(pass_id))
+    k = t.get("passes", {}).get(("r" if reduced else "") + str(pass_id))
     return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def roofline(prof, reduced):
+    """(roofline of the kernel with the most timed milliseconds, the others)."""
+    if not prof:
+        return None
+    timed_ids = [k for k in PASS_NAMES if prof.get(k) and prof[k][0] and prof[k][1] > 0]
+    if not timed_ids:
+        return None
+    kid = max(timed_ids, key=lambda k: prof[k][1])
+    n_l, ms, by = prof[kid]
+    ach = (by / n_l) / (ms / n_l * 1e-3) / 1e9
+    main_rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kid, reduced),
+               "kernel": PASS_NAMES[kid], "launches": n_l, "avg_us": round(1000 * ms / n_l, 2),
+               "alg_bytes_per_launch": round(by / n_l)}
+    others = []
+    for k in timed_ids:
+        if k != kid:
+            n2, ms2, by2 = prof[k]
+            others.append({"kernel": PASS_NAMES[k], "launches": n2,
+                           "avg_us": round(1000 * ms2 / n2, 2),
+                           "achieved": round((by2 / n2) / (ms2 / n2 * 1e-3) / 1e9, 1),
+                           "share_of_timed_ms": round(ms2 / sum(prof[j][1] for j in timed_ids), 3)})
+    main_rl["share_of_timed_ms"] = round(ms / sum(prof[j][1] for j in timed_ids), 3)
+    return main_rl, others
 
 
 def cpu_baseline(insts, budget_s):

@@ -517,8 +517,9 @@ struct glm_factor {
   glm_stats stats{};
   bool prof = false;
   std::vector<EventPair> ev_used, ev_free;
-  int64_t prof_launch[2] = {0, 0};
-  double prof_ms[2] = {0, 0};
+  int64_t prof_launch[3] = {0, 0, 0};
+  double prof_ms[3] = {0, 0, 0};
+  double prof_bytes_host = 0.0;   // reduced handle: algorithmic bytes of the timed applies
   int launches = 0;
 
   template <typename T>
@@ -928,6 +929,38 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
 
 namespace {
 
+// One block-reflector apply over the batch; while profiling, bracketed by HIP
+// events (kernel id 2) with its algorithmic bytes counted on the host: the
+// target rows [c0, M) read and written once plus the panel's V read once.
+hipError_t timed_apply(glm_factor* f, int p, const double* W, const double* T, double* C,
+                       int target_w, int trans, int maxcols, hipStream_t s) {
+  const RedPlan& r = f->rp;
+  const RedDesc* dd = f->at<RedDesc>(r.o_desc);
+  EventPair e{};
+  if (f->prof) {
+    e = get_event(f, 2);
+    if (hipError_t x = hipEventRecord(e.a, s)) return x;
+    const int c0 = p * RED_PANEL;
+    double by = 0.0;
+    for (const RedDesc& d : r.d) {
+      if (c0 >= d.kr) continue;
+      const int w = std::min(RED_PANEL, d.kr - c0);
+      const double rows = (double)(d.M - c0);
+      const double ncols = target_w ? (double)(d.n - c0 - w) : (double)d.G * d.K;
+      if (ncols <= 0) continue;
+      by += rows * (16.0 * ncols + 8.0 * w);
+    }
+    f->prof_bytes_host += by;
+  }
+  hipError_t x = launch_red_apply(dd, r.B, p, W, T, C, target_w, trans, maxcols, s);
+  if (x) return x;
+  if (f->prof) {
+    if (hipError_t y = hipEventRecord(e.b, s)) return y;
+    f->ev_used.push_back(e);
+  }
+  return hipSuccess;
+}
+
 // glm_qr_factor with GLM_REDUCED: copy X, factor W = [X_1 ... X_G] panel by
 // panel (each panel's block reflector applied to the columns right of it),
 // take the reduced regressors from R and factor the reduced problem in the
@@ -965,7 +998,7 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
   if (!e) e = hipMemcpyAsync(W, X, 8 * r.sumMn, hipMemcpyDeviceToDevice, stream);
   for (int p = 0; p < r.maxpan && !e; ++p) {
     e = launch_red_panel(dd, r.B, p, W, f->at<double>(r.o_tau), T, stream);
-    if (!e) e = launch_red_apply(dd, r.B, p, W, T, W, 1, 1, r.maxn - p * RED_PANEL, stream);
+    if (!e) e = timed_apply(f, p, W, T, W, 1, 1, r.maxn - p * RED_PANEL, stream);
   }
   if (!e) e = launch_red_extract(dd, r.B, W, nullptr, f->at<double>(r.o_Xr), nullptr, stream);
   if (e != hipSuccess) {
@@ -995,7 +1028,7 @@ int solve_reduced(glm_factor* f, const double* Omega, const double* y, const dou
   double* ur = f->at<double>(rp.o_ur);
   GLM_CHECK(hipMemcpyAsync(Yt, y, 8 * rp.sumMGK, hipMemcpyDeviceToDevice, stream));
   for (int p = 0; p < rp.maxpan; ++p)
-    GLM_CHECK(launch_red_apply(dd, rp.B, p, W, T, Yt, 0, 1, rp.maxGK, stream));
+    GLM_CHECK(timed_apply(f, p, W, T, Yt, 0, 1, rp.maxGK, stream));
   GLM_CHECK(launch_red_extract(dd, rp.B, W, Yt, nullptr, f->at<double>(rp.o_yr), stream));
   int rc = glm_gls_solve(f->sub, Omega, f->at<double>(rp.o_yr), r, tol, max_iter, beta, ur, uc,
                          info, iters, stream);
@@ -1003,7 +1036,7 @@ int solve_reduced(glm_factor* f, const double* Omega, const double* y, const dou
   GLM_CHECK(launch_red_tail(dd, rp.B, rp.maxM, Omega, f->at<double>(rp.o_Oinv), Yt, ur, u, info,
                             stream));
   for (int p = rp.maxpan - 1; p >= 0; --p)
-    GLM_CHECK(launch_red_apply(dd, rp.B, p, W, T, u, 0, 0, rp.maxGK, stream));
+    GLM_CHECK(timed_apply(f, p, W, T, u, 0, 0, rp.maxGK, stream));
   f->stats = f->sub->stats;
   f->stats.launches += 2 * rp.maxpan + 2;
   return GLM_OK;
@@ -1156,15 +1189,25 @@ int glm_get_stats(const glm_factor* f, glm_stats* out) {
 
 int glm_profile_enable(glm_factor* f, int on) {
   if (!f) return GLM_EINVAL;
-  if (f->reduced) return glm_profile_enable(f->sub, on);
+  if (f->reduced) {
+    f->prof = on != 0;
+    return glm_profile_enable(f->sub, on);
+  }
   f->prof = on != 0;
   return GLM_OK;
 }
 
 int glm_profile_read(glm_factor* f, int kernel_id, int64_t* launches, double* total_ms,
                      double* total_bytes) {
-  if (!f || kernel_id < 0 || kernel_id > 1) return GLM_EINVAL;
-  if (f->reduced) return glm_profile_read(f->sub, kernel_id, launches, total_ms, total_bytes);
+  if (!f || kernel_id < 0 || kernel_id > 2) return GLM_EINVAL;
+  if (f->reduced && kernel_id < 2)
+    return glm_profile_read(f->sub, kernel_id, launches, total_ms, total_bytes);
+  if (!f->reduced && kernel_id == 2) {
+    if (launches) *launches = 0;
+    if (total_ms) *total_ms = 0.0;
+    if (total_bytes) *total_bytes = 0.0;
+    return GLM_OK;
+  }
   if (hipDeviceSynchronize() != hipSuccess) return GLM_EHIP;
   for (auto& e : f->ev_used) {
     float ms = 0.f;
@@ -1174,6 +1217,16 @@ int glm_profile_read(glm_factor* f, int kernel_id, int64_t* launches, double* to
     f->ev_free.push_back(e);
   }
   f->ev_used.clear();
+  if (f->reduced) {
+    // block-reflector applies: bytes counted on the host when launched
+    if (launches) *launches = f->prof_launch[2];
+    if (total_ms) *total_ms = f->prof_ms[2];
+    if (total_bytes) *total_bytes = f->prof_bytes_host;
+    f->prof_launch[2] = 0;
+    f->prof_ms[2] = 0.0;
+    f->prof_bytes_host = 0.0;
+    return GLM_OK;
+  }
   unsigned long long hb[2] = {0, 0};
   if (hipMemcpy(hb, f->ws + f->p.o_bytes, sizeof(hb), hipMemcpyDeviceToHost) != hipSuccess)
     return GLM_EHIP;

@@ -102,6 +102,11 @@ def unpack(lay: BatchLayout, flat, kind: str):
     return out
 
 
+# kernel ids of glm_profile_read: the iteration launches of projection passes
+# A and B, and (reduced solvers) the block-reflector applications
+PROFILED_KERNELS = (0, 1, 2)
+
+
 class SURSolver:
     """Owns one workspace and one factor handle for a fixed batch shape."""
 
@@ -125,7 +130,7 @@ class SURSolver:
         self._X = None
         self._Rc = None
         self._profile = False
-        self._prof_acc = {0: [0, 0.0, 0.0], 1: [0, 0.0, 0.0]}
+        self._prof_acc = {kid: [0, 0.0, 0.0] for kid in PROFILED_KERNELS}
 
     @property
     def workspace_bytes(self) -> int:
@@ -133,7 +138,7 @@ class SURSolver:
 
     def _harvest_profile(self):
         if self._profile and self.handle is not None:
-            for kid in (0, 1):
+            for kid in PROFILED_KERNELS:
                 n, ms, by = _lib.glm_profile_read(self.handle, kid)
                 acc = self._prof_acc[kid]
                 acc[0] += n
