@@ -26,7 +26,7 @@ namespace glm {
 namespace {
 
 constexpr int RP = RED_PANEL;
-constexpr int RCH = 64;   // rows of V staged in LDS per chunk
+constexpr int RCH = 128;  // rows of V staged in LDS per chunk
 
 // V[r][j] of panel rows r (relative to the panel's first row): the unit
 // diagonal and zeros above it are implicit in the stored factorization.
@@ -106,7 +106,7 @@ k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
 // columns), lane per column: z = V^T c, then z' = op(T) z, then c -= V z',
 // with V staged in LDS RCH rows at a time and RU rows of c loaded before
 // they are used.
-constexpr int RU = 8;
+constexpr int RU = 32;
 
 __global__ void __launch_bounds__(QNT)
 k_red_apply(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
