@@ -418,9 +418,10 @@ struct RedPlan {
   std::vector<RedDesc> d;
   std::vector<int32_t> G, M, K, k, n;
   glm_shape sub{};
-  int64_t sumMn = 0, sumMGK = 0, sumMrn = 0, sumMrGK = 0, sumn = 0, sumT = 0, sumG2 = 0;
+  int64_t sumMn = 0, sumMGK = 0, sumMrn = 0, sumMrGK = 0, sumn = 0, sumT = 0, sumG2 = 0,
+          sumZp = 0;
   size_t o_desc = 0, o_W = 0, o_tau = 0, o_T = 0, o_Yt = 0, o_Xr = 0, o_yr = 0, o_ur = 0,
-         o_Oinv = 0, o_sub = 0, sub_bytes = 0, total = 0;
+         o_Oinv = 0, o_Zp = 0, o_sub = 0, sub_bytes = 0, total = 0;
 };
 
 int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
@@ -449,6 +450,7 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     d.tau_off = r.sumn;
     d.t_off = r.sumT;
     d.om_off = om;
+    d.zp_off = r.sumZp;
     const int npan = (d.kr + RED_PANEL - 1) / RED_PANEL;
     r.maxpan = std::max(r.maxpan, npan);
     r.maxn = std::max(r.maxn, n);
@@ -460,6 +462,8 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     r.sumMrGK += (int64_t)d.Mr * d.G * d.K;
     r.sumn += n;
     r.sumT += (int64_t)npan * RED_PANEL * RED_PANEL;
+    r.sumZp += (int64_t)((d.M + RED_SEG - 1) / RED_SEG) * RED_PANEL *
+               std::max(n, d.G * d.K);
     om += (int64_t)d.G * d.G;
     r.sumG2 = om;
     rhs += d.K;
@@ -498,6 +502,7 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
   r.o_yr = take(8 * r.sumMrGK);
   r.o_ur = take(8 * r.sumMrGK);
   r.o_Oinv = take(8 * r.sumG2);
+  r.o_Zp = take(8 * r.sumZp);
   r.o_sub = take(r.sub_bytes);
   r.total = o;
   return GLM_OK;
@@ -952,7 +957,8 @@ hipError_t timed_apply(glm_factor* f, int p, const double* W, const double* T, d
     }
     f->prof_bytes_host += by;
   }
-  hipError_t x = launch_red_apply(dd, r.B, p, W, T, C, target_w, trans, maxcols, s);
+  hipError_t x = launch_red_apply(dd, r.B, p, W, T, C, f->at<double>(r.o_Zp), target_w, trans,
+                                  maxcols, r.maxM - p * RED_PANEL, s);
   if (x) return x;
   if (f->prof) {
     if (hipError_t y = hipEventRecord(e.b, s)) return y;

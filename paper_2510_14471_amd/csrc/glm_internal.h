@@ -103,8 +103,11 @@ struct RedDesc {
   int64_t tau_off; // reflector scalars (n)
   int64_t t_off;   // block-reflector factors T (panels x 32 x 32)
   int64_t om_off;  // Omega (G x G)
+  int64_t zp_off;  // partial products V^T C of the row segments
+                   // (ceil(M / RED_SEG) x 32 x max(n, G K))
 };
 constexpr int RED_PANEL = 32;    // columns per Householder panel
+constexpr int RED_SEG = 1024;    // rows per workgroup of a block-reflector apply
 
 // Arguments of the two projection-pass kernels (host side).
 template <typename T>
@@ -217,8 +220,8 @@ hipError_t launch_update_c(const InstDesc* insts, int B, const RhsState* st,
 hipError_t launch_red_panel(const RedDesc* d, int B, int panel, double* W, double* tau,
                            double* T, hipStream_t s);
 hipError_t launch_red_apply(const RedDesc* d, int B, int panel, const double* W,
-                           const double* T, double* C, int target_w, int trans, int maxcols,
-                           hipStream_t s);
+                           const double* T, double* C, double* Zp, int target_w, int trans,
+                           int maxcols, int maxrows, hipStream_t s);
 hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, const double* Yt,
                              double* Xr, double* yr, hipStream_t s);
 hipError_t launch_red_tail(const RedDesc* d, int B, int maxM, const double* Om, double* Oinv,

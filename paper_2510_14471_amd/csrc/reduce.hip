@@ -9,7 +9,7 @@
 // Q = B_0 B_1 ... with B_p = I - V_p T_p V_p^T (T_p upper triangular):
 //   k_red_panel    factor panel p in place (reflectors below the diagonal),
 //                  store tau and T_p
-//   k_red_apply    C <- B_p^T C (the trailing columns of W while factoring,
+//   k_red_apply_z/_c  C <- B_p^T C (the trailing columns of W while factoring,
 //                  and Y for Q^T Y) or C <- B_p C (Q Z for the residual)
 //   k_red_extract  reduced regressors (R rows) and reduced responses
 //   k_red_oinv     Omega^-1 per instance
@@ -102,33 +102,99 @@ k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
 
 // C <- (I - V op(T) V^T) C on rows [c0, M) of one instance, op(T) = T^T when
 // trans (B_p^T) else T (B_p).  Target: the trailing columns of W (target_w)
-// or the M x (G K) vector array C.  Workgroup (instance, chunk of QNT
-// columns), lane per column: z = V^T c, then z' = op(T) z, then c -= V z',
-// with V staged in LDS RCH rows at a time and RU rows of c loaded before
+// or the M x (G K) vector array C.  The rows are cut into segments of
+// RED_SEG, so that a tall instance spreads over as many workgroups as a short
+// one has rows to spare; workgroup (instance, chunk of QNT columns, segment),
+// lane per column:
+//   k_red_apply_z   partial z_s = V_s^T c_s of the segment
+//   k_red_apply_c   z = sum of the partials (fixed order), z' = op(T) z,
+//                   c_s -= V_s z'
+// V is staged in LDS RCH rows at a time and RU rows of c are loaded before
 // they are used.
 constexpr int RU = 32;
+static_assert(RED_SEG % RCH == 0 && RCH % RU == 0, "segment, chunk and batch sizes nest");
+
+struct ApplyTarget {
+  const double* a0;  // panel block of the reflectors (row c0, column c0)
+  double* cb;        // row c0 of the target
+  int w, rows, ncols, ld, seg_rows, r_seg;
+};
+
+// the apply's target for this workgroup, or false when it has nothing to do
+__device__ __forceinline__ bool apply_target(const RedDesc& d, int panel, const double* W,
+                                             double* C, int target_w, ApplyTarget& a) {
+  const int c0 = panel * RP;
+  if (c0 >= d.kr) return false;
+  a.w = min(RP, d.kr - c0);
+  a.rows = d.M - c0;
+  a.a0 = W + d.w_off + (int64_t)c0 * d.n + c0;
+  if (target_w) {
+    a.ncols = d.n - c0 - a.w;
+    a.ld = d.n;
+    a.cb = C + d.w_off + (int64_t)c0 * d.n + c0 + a.w;
+  } else {
+    a.ncols = d.G * d.K;
+    a.ld = a.ncols;
+    a.cb = C + d.v_off + (int64_t)c0 * a.ld;
+  }
+  if ((int)blockIdx.y * QNT >= a.ncols) return false;
+  a.r_seg = blockIdx.z * RED_SEG;
+  if (a.r_seg >= a.rows) return false;
+  a.seg_rows = min(RED_SEG, a.rows - a.r_seg);
+  return true;
+}
+
+__device__ __forceinline__ void stage_v(double (*Vs)[RP + 1], const ApplyTarget& a, int ldw,
+                                        int r0) {
+  for (int e = threadIdx.x; e < RCH * RP; e += QNT) {
+    const int r = e / RP, j = e % RP;
+    Vs[r][j] = vpanel(a.a0, ldw, r0 + r, j, a.rows, a.w);
+  }
+}
 
 __global__ void __launch_bounds__(QNT)
-k_red_apply(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
-            const double* __restrict__ T, double* __restrict__ C, int target_w, int trans) {
+k_red_apply_z(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
+              double* __restrict__ C, double* __restrict__ Zp, int target_w) {
   const RedDesc d = descs[blockIdx.x];
-  const int c0 = panel * RP;
-  if (c0 >= d.kr) return;
-  const int w = min(RP, d.kr - c0), rows = d.M - c0;
-  const double* a0 = W + d.w_off + (int64_t)c0 * d.n + c0;
-  int ncols, ld;
-  double* cb;
-  if (target_w) {
-    ncols = d.n - c0 - w;
-    ld = d.n;
-    cb = C + d.w_off + (int64_t)c0 * d.n + c0 + w;
-  } else {
-    ncols = d.G * d.K;
-    ld = ncols;
-    cb = C + d.v_off + (int64_t)c0 * ld;
+  ApplyTarget a;
+  if (!apply_target(d, panel, W, C, target_w, a)) return;
+  __shared__ double Vs[RCH][RP + 1];
+  const int col = blockIdx.y * QNT + threadIdx.x;
+  const bool ok = col < a.ncols;
+  const double* cc = a.cb + col;
+  double z[RP];
+#pragma unroll
+  for (int j = 0; j < RP; ++j) z[j] = 0.0;
+  for (int r0 = a.r_seg; r0 < a.r_seg + a.seg_rows; r0 += RCH) {
+    __syncthreads();
+    stage_v(Vs, a, d.n, r0);
+    __syncthreads();
+    const int nr = min(RCH, a.r_seg + a.seg_rows - r0);
+    for (int r = 0; r < nr; r += RU) {
+      double x[RU];
+#pragma unroll
+      for (int q = 0; q < RU; ++q)
+        x[q] = (ok && r + q < nr) ? cc[(int64_t)(r0 + r + q) * a.ld] : 0.0;
+#pragma unroll
+      for (int q = 0; q < RU; ++q)
+#pragma unroll
+        for (int j = 0; j < RP; ++j) z[j] += Vs[r + q][j] * x[q];
+    }
   }
-  const int col0 = blockIdx.y * QNT;
-  if (col0 >= ncols) return;
+  if (ok) {
+    double* zp = Zp + d.zp_off + (int64_t)blockIdx.z * RP * a.ncols + col;
+#pragma unroll
+    for (int j = 0; j < RP; ++j) zp[(int64_t)j * a.ncols] = z[j];
+  }
+}
+
+__global__ void __launch_bounds__(QNT)
+k_red_apply_c(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
+              const double* __restrict__ T, double* __restrict__ C,
+              const double* __restrict__ Zp, int target_w, int trans) {
+  const RedDesc d = descs[blockIdx.x];
+  ApplyTarget a;
+  if (!apply_target(d, panel, W, C, target_w, a)) return;
   __shared__ double Ts[RP][RP + 1];
   __shared__ double Vs[RCH][RP + 1];
   const int tid = threadIdx.x;
@@ -139,31 +205,20 @@ k_red_apply(const RedDesc* __restrict__ descs, int panel, const double* __restri
       Ts[i][j] = trans ? Tp[j * RP + i] : Tp[i * RP + j];
     }
   }
-  const int col = col0 + tid;
-  const bool ok = col < ncols;
-  double* cc = cb + col;
+  const int col = blockIdx.y * QNT + tid;
+  const bool ok = col < a.ncols;
+  double* cc = a.cb + col;
   double z[RP];
 #pragma unroll
   for (int j = 0; j < RP; ++j) z[j] = 0.0;
-  for (int r0 = 0; r0 < rows; r0 += RCH) {
-    __syncthreads();
-    for (int e = tid; e < RCH * RP; e += QNT) {
-      const int r = e / RP, j = e % RP;
-      Vs[r][j] = vpanel(a0, d.n, r0 + r, j, rows, w);
-    }
-    __syncthreads();
-    const int nr = min(RCH, rows - r0);
-    for (int r = 0; r < nr; r += RU) {
-      double x[RU];
+  if (ok) {
+    const int nseg = (a.rows + RED_SEG - 1) / RED_SEG;
+    const double* zp = Zp + d.zp_off + col;
+    for (int s = 0; s < nseg; ++s)
 #pragma unroll
-      for (int q = 0; q < RU; ++q)
-        x[q] = (ok && r + q < nr) ? cc[(int64_t)(r0 + r + q) * ld] : 0.0;
-#pragma unroll
-      for (int q = 0; q < RU; ++q)
-#pragma unroll
-        for (int j = 0; j < RP; ++j) z[j] += Vs[r + q][j] * x[q];
-    }
+      for (int j = 0; j < RP; ++j) z[j] += zp[((int64_t)s * RP + j) * a.ncols];
   }
+  __syncthreads();  // Ts
   double zz[RP];
 #pragma unroll
   for (int i = 0; i < RP; ++i) {
@@ -172,26 +227,23 @@ k_red_apply(const RedDesc* __restrict__ descs, int panel, const double* __restri
     for (int j = 0; j < RP; ++j) s += Ts[i][j] * z[j];
     zz[i] = s;
   }
-  for (int r0 = 0; r0 < rows; r0 += RCH) {
+  for (int r0 = a.r_seg; r0 < a.r_seg + a.seg_rows; r0 += RCH) {
     __syncthreads();
-    for (int e = tid; e < RCH * RP; e += QNT) {
-      const int r = e / RP, j = e % RP;
-      Vs[r][j] = vpanel(a0, d.n, r0 + r, j, rows, w);
-    }
+    stage_v(Vs, a, d.n, r0);
     __syncthreads();
-    const int nr = min(RCH, rows - r0);
+    const int nr = min(RCH, a.r_seg + a.seg_rows - r0);
     if (ok)
       for (int r = 0; r < nr; r += RU) {
         double x[RU];
 #pragma unroll
         for (int q = 0; q < RU; ++q)
-          x[q] = (r + q < nr) ? cc[(int64_t)(r0 + r + q) * ld] : 0.0;
+          x[q] = (r + q < nr) ? cc[(int64_t)(r0 + r + q) * a.ld] : 0.0;
 #pragma unroll
         for (int q = 0; q < RU; ++q) {
           double v = x[q];
 #pragma unroll
           for (int j = 0; j < RP; ++j) v -= Vs[r + q][j] * zz[j];
-          if (r + q < nr) cc[(int64_t)(r0 + r + q) * ld] = v;
+          if (r + q < nr) cc[(int64_t)(r0 + r + q) * a.ld] = v;
         }
       }
   }
@@ -302,12 +354,14 @@ hipError_t launch_red_panel(const RedDesc* d, int B, int panel, double* W, doubl
 }
 
 hipError_t launch_red_apply(const RedDesc* d, int B, int panel, const double* W,
-                           const double* T, double* C, int target_w, int trans, int maxcols,
-                           hipStream_t s) {
-  if (B <= 0 || maxcols <= 0) return hipSuccess;
-  const int chunks = (maxcols + QNT - 1) / QNT;
-  hipLaunchKernelGGL(k_red_apply, dim3(B, chunks), dim3(QNT), 0, s, d, panel, W, T, C,
-                     target_w, trans);
+                           const double* T, double* C, double* Zp, int target_w, int trans,
+                           int maxcols, int maxrows, hipStream_t s) {
+  if (B <= 0 || maxcols <= 0 || maxrows <= 0) return hipSuccess;
+  const dim3 grid(B, (maxcols + QNT - 1) / QNT, (maxrows + RED_SEG - 1) / RED_SEG);
+  hipLaunchKernelGGL(k_red_apply_z, grid, dim3(QNT), 0, s, d, panel, W, C, Zp, target_w);
+  if (hipError_t e = hipGetLastError()) return e;
+  hipLaunchKernelGGL(k_red_apply_c, grid, dim3(QNT), 0, s, d, panel, W, T, C,
+                     (const double*)Zp, target_w, trans);
   return hipGetLastError();
 }
 
