@@ -30,6 +30,9 @@ constexpr size_t kRowOmegaLds = 64 * 1024; // largest Omega the row-vector passe
 constexpr int kRowsPerLane = 16;            // row-vector passes: rows per lane and sub-tile
 constexpr int kTargetTiles = 12288;       // row tiles over the whole batch (equal cost)
 constexpr int kMinTileRows = 16;          // keeps the per-tile partial sums small
+// streaming cost (elements) below which a tile is not cut: a small batch (the
+// n + 1 rows of a reduced model) gets fewer, larger tiles
+constexpr double kMinTileCost = 32768.0;
 constexpr int kPollEvery = 8;             // iterations between host convergence polls
 // Stagnation windows: iterations in which c must at least halve.  Slowly
 // converging systems (singular Omega with a wide nonzero spectrum) need
@@ -187,7 +190,7 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
       total_cost += (double)s->M[b] * (double)(nb + 3 * (int64_t)s->G[b] * s->K[b]);
     }
   }
-  const double tile_cost = std::max(1.0, total_cost / kTargetTiles);
+  const double tile_cost = std::max(kMinTileCost, total_cost / kTargetTiles);
   (void)sum_rows;
   // FP64 solves run in both modes (in the mixed path as the continuation of
   // a refinement the FP32 inner solves no longer advance)

@@ -107,7 +107,7 @@ struct RedDesc {
                    // (ceil(M / RED_SEG) x 32 x max(n, G K))
 };
 constexpr int RED_PANEL = 32;    // columns per Householder panel
-constexpr int RED_SEG = 1024;    // rows per workgroup of a block-reflector apply
+constexpr int RED_SEG = 512;     // rows per workgroup of a block-reflector apply
 
 // Arguments of the two projection-pass kernels (host side).
 template <typename T>

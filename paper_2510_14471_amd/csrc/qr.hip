@@ -220,6 +220,10 @@ k_qr(const QRJob* __restrict__ jobs, double* __restrict__ A,
   }
 }
 
+// rows in flight per lane in the per-block factorization and Q formation
+constexpr int K32_U = 8;
+constexpr int K32_SLOTS = QNT / 32;
+
 __global__ void __launch_bounds__(QNT)
 k_qr32(const QRJob* __restrict__ jobs, double* __restrict__ A, double* __restrict__ Rout,
        int* __restrict__ flags) {
@@ -227,7 +231,7 @@ k_qr32(const QRJob* __restrict__ jobs, double* __restrict__ A, double* __restric
   const int rows = job.rows, cols = job.cols, ld = job.ld;
   double* __restrict__ a0 = A + job.a_off;
 
-  __shared__ Qr32Shared sh;
+  __shared__ Qr32Shared<QNT> sh;
   __shared__ double fro2;
   double (*red)[QW] = sh.red;
   double* dsum = sh.dsum;
@@ -237,7 +241,7 @@ k_qr32(const QRJob* __restrict__ jobs, double* __restrict__ A, double* __restric
   const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
   const bool colok = c < cols;
 
-  qr32_factor(a0, rows, cols, ld, sh);
+  qr32_factor<QNT, K32_U>(a0, rows, cols, ld, sh);
 
   // ---- R out (upper triangle of the first cols rows), rank check ---------
   if (tid == 0) fro2 = 0.0;
@@ -270,18 +274,18 @@ k_qr32(const QRJob* __restrict__ jobs, double* __restrict__ A, double* __restric
     double dot = 0.0;
     // rows above lo: column j becomes zero (row j-1 is handled in the sweep)
     for (int t = tid; t < lo && t < rows; t += QNT) a0[(int64_t)t * ld + j] = 0.0;
-    // the sweep starts at a multiple of QR_SLOTS * QR_U, so that a row is
+    // the sweep starts at a multiple of K32_SLOTS * K32_U, so that a row is
     // loaded and stored by the same half-wave in every pass
-    for (int t0 = lo & ~(QR_SLOTS * QR_U - 1); t0 < rows; t0 += QR_SLOTS * QR_U) {
-      double a[QR_U];
+    for (int t0 = lo & ~(K32_SLOTS * K32_U - 1); t0 < rows; t0 += K32_SLOTS * K32_U) {
+      double a[K32_U];
 #pragma unroll
-      for (int u = 0; u < QR_U; ++u) {
-        const int t = t0 + slot + QR_SLOTS * u;
+      for (int u = 0; u < K32_U; ++u) {
+        const int t = t0 + slot + K32_SLOTS * u;
         a[u] = (t < rows && t >= lo && colok && c >= lo) ? a0[(int64_t)t * ld + c] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < QR_U; ++u) {
-        const int t = t0 + slot + QR_SLOTS * u;
+      for (int u = 0; u < K32_U; ++u) {
+        const int t = t0 + slot + K32_SLOTS * u;
         const bool rok = t < rows && t >= lo;
         double x = a[u];
         // columns j and j-1 of this row as loaded (this pass changes columns >= j)
@@ -306,7 +310,7 @@ k_qr32(const QRJob* __restrict__ jobs, double* __restrict__ A, double* __restric
     }
     __syncthreads();
     if (j >= 1) {
-      col_sum(dot, j, cols, red, dsum);
+      col_sum<QNT>(dot, j, cols, red, dsum);
       if (tid >= j && tid < cols) wk[tid] = dsum[tid];
       __syncthreads();
     }

@@ -27,14 +27,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Factorization of blocks of at most 32 columns with the data mapping turned
 // around against the row-per-lane form: lane l owns column l % 32, and the row slot
-// 2 w + l / 32 of wave w takes rows slot, slot + 8, ...  A row segment is then
-// one coalesced access, QR_U rows per lane are in flight at once, the dot
+// 2 w + l / 32 of wave w takes rows slot, slot + NT / 32, ...  A row segment is
+// then one coalesced access, U rows per lane are in flight at once, the dot
 // products are one register per lane, and the pivot-column entry of a row
 // comes from its lane by a shuffle.  Arithmetic and order of the updates
-// follow k_qr; only the summation order of the dot products differs.
-constexpr int QR_U = 32;                 // rows in flight per lane
-constexpr int QR_SLOTS = QNT / 32;       // row slots per workgroup
-static_assert(((QR_SLOTS * QR_U) & (QR_SLOTS * QR_U - 1)) == 0, "rows per sweep step: a power of two");
+// follow k_qr; only the summation order of the dot products differs.  NT is
+// the workgroup size (a multiple of 64).
 
 // value of column col in the row this lane's half-wave holds
 __device__ __forceinline__ double shfl_col(double v, int col) {
@@ -42,7 +40,8 @@ __device__ __forceinline__ double shfl_col(double v, int col) {
 }
 
 // dsum[k] = sum of dot over the workgroup's lanes of column k, k in [lo, cols)
-__device__ __forceinline__ void col_sum(double dot, int lo, int cols, double (*red)[QW],
+template <int NT>
+__device__ __forceinline__ void col_sum(double dot, int lo, int cols, double (*red)[NT / 64],
                                         double* dsum) {
   const int tid = threadIdx.x;
   dot += __shfl_xor(dot, 32, 64);
@@ -51,7 +50,7 @@ __device__ __forceinline__ void col_sum(double dot, int lo, int cols, double (*r
   if (tid >= lo && tid < cols) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < QW; ++q) s += red[tid][q];
+    for (int q = 0; q < NT / 64; ++q) s += red[tid][q];
     dsum[tid] = s;
   }
   __syncthreads();
@@ -61,8 +60,9 @@ __device__ __forceinline__ void col_sum(double dot, int lo, int cols, double (*r
 // row stride ld, in place (R on and above the diagonal, the reflectors below,
 // LAPACK geqr2 convention); tau_s receives the reflector scalars.  Called by
 // every thread of the workgroup.
+template <int NT>
 struct Qr32Shared {
-  double red[32][QW];
+  double red[32][NT / 64];
   double dsum[32];
   double pivrow[32];
   double wk[32];
@@ -70,9 +70,13 @@ struct Qr32Shared {
   double par[3];
 };
 
+template <int NT, int U>
 __device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
-                            Qr32Shared& sh) {
-  double (*red)[QW] = sh.red;
+                            Qr32Shared<NT>& sh) {
+  constexpr int SLOTS = NT / 32;   // row slots per workgroup
+  static_assert(NT % 64 == 0 && ((SLOTS * U) & (SLOTS * U - 1)) == 0,
+                "whole waves; rows per sweep step a power of two");
+  double (*red)[NT / 64] = sh.red;
   double* dsum = sh.dsum;
   double* pivrow = sh.pivrow;
   double* wk = sh.wk;
@@ -88,18 +92,18 @@ __device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
     const double wkc = (p > 0 && c > j && colok) ? wk[c] : 0.0;
     const int lo = (j > 0) ? j : 0;
     double dot = 0.0;
-    // the sweep starts at a multiple of QR_SLOTS * QR_U, so that a row is
+    // the sweep starts at a multiple of SLOTS * U, so that a row is
     // loaded and stored by the same half-wave in every pass
-    for (int t0 = lo & ~(QR_SLOTS * QR_U - 1); t0 < rows; t0 += QR_SLOTS * QR_U) {
-      double a[QR_U];
+    for (int t0 = lo & ~(SLOTS * U - 1); t0 < rows; t0 += SLOTS * U) {
+      double a[U];
 #pragma unroll
-      for (int u = 0; u < QR_U; ++u) {
-        const int t = t0 + slot + QR_SLOTS * u;
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + slot + SLOTS * u;
         a[u] = (t < rows && t >= lo && colok && c >= lo) ? a0[(int64_t)t * ld + c] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < QR_U; ++u) {
-        const int t = t0 + slot + QR_SLOTS * u;
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + slot + SLOTS * u;
         const bool rok = t < rows && t >= lo;
         double x = a[u];
         if (p > 0) {
@@ -119,7 +123,7 @@ __device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
     }
     if (p == cols) break;
     __syncthreads();  // pivrow visible, all rows written
-    col_sum(dot, p, cols, red, dsum);
+    col_sum<NT>(dot, p, cols, red, dsum);
     if (tid == 0) {
       const double alpha = pivrow[p];
       const double xnorm2 = dsum[p];            // squared norm below the pivot

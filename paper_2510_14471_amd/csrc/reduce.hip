@@ -37,7 +37,13 @@ __device__ __forceinline__ double vpanel(const double* __restrict__ a0, int ld, 
   return r > j ? a0[(int64_t)r * ld + j] : 0.0;
 }
 
-__global__ void __launch_bounds__(QNT)
+// The panel kernel runs RPNT threads per instance: the panel passes are
+// sequential over the rows, so the rows in flight per instance set its time.
+constexpr int RPNT = 1024;
+constexpr int RPU = 16;             // rows in flight per lane in the panel passes
+constexpr int RPW = RPNT / 64;      // waves per panel workgroup
+
+__global__ void __launch_bounds__(RPNT)
 k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W,
             double* __restrict__ tau, double* __restrict__ T) {
   const RedDesc d = descs[blockIdx.x];
@@ -45,22 +51,22 @@ k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
   if (c0 >= d.kr) return;
   const int w = min(RP, d.kr - c0), rows = d.M - c0, ld = d.n;
   double* a0 = W + d.w_off + (int64_t)c0 * ld + c0;
-  __shared__ Qr32Shared sh;
+  __shared__ Qr32Shared<RPNT> sh;
   __shared__ double S[RP][RP + 1];
-  __shared__ double part[QW][RP][RP];
-  qr32_factor(a0, rows, w, ld, sh);
+  __shared__ double part[4][RP][RP];
+  qr32_factor<RPNT, RPU>(a0, rows, w, ld, sh);
   const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
   if (tid < w) tau[d.tau_off + c0 + tid] = sh.tau_s[tid];
   // S = V^T V: lane c accumulates S[i][c] for every i over its rows
   double acc[RP];
 #pragma unroll
   for (int i = 0; i < RP; ++i) acc[i] = 0.0;
-  // rows r0 + slot + QR_SLOTS q: the same half-wave that factored them
+  // rows r0 + slot + (RPNT / 32) q: the same half-wave that factored them
   constexpr int SU = 4;
-  for (int r0 = 0; r0 < rows; r0 += QR_SLOTS * SU) {
+  for (int r0 = 0; r0 < rows; r0 += (RPNT / 32) * SU) {
     double v[SU];
 #pragma unroll
-    for (int q = 0; q < SU; ++q) v[q] = vpanel(a0, ld, r0 + slot + QR_SLOTS * q, c, rows, w);
+    for (int q = 0; q < SU; ++q) v[q] = vpanel(a0, ld, r0 + slot + (RPNT / 32) * q, c, rows, w);
 #pragma unroll
     for (int q = 0; q < SU; ++q)
 #pragma unroll
@@ -68,22 +74,29 @@ k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
   }
 #pragma unroll
   for (int i = 0; i < RP; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
-  if ((tid & 63) < 32)
+  // wave partials summed in four slots, four waves at a time in wave order
+  const int wave = tid >> 6;
+  for (int g = 0; g < RPW / 4; ++g) {
+    if (wave / 4 == g && (tid & 63) < 32)
 #pragma unroll
-    for (int i = 0; i < RP; ++i) part[tid >> 6][i][c] = acc[i];
-  __syncthreads();
-  for (int e = tid; e < RP * RP; e += QNT) {
+      for (int i = 0; i < RP; ++i) {
+        if (g == 0) part[wave & 3][i][c] = acc[i];
+        else part[wave & 3][i][c] += acc[i];
+      }
+    __syncthreads();
+  }
+  for (int e = tid; e < RP * RP; e += RPNT) {
     const int i = e / RP, j = e % RP;
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < QW; ++q) s += part[q][i][j];
+    for (int q = 0; q < 4; ++q) s += part[q][i][j];
     S[i][j] = s;
   }
   __syncthreads();
   // T (forward, columnwise): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j];
   // built in LDS (the partial sums are no longer needed) by one thread
   double (*Tl)[RP] = part[0];
-  for (int e = tid; e < RP * RP; e += QNT) Tl[e / RP][e % RP] = 0.0;
+  for (int e = tid; e < RP * RP; e += RPNT) Tl[e / RP][e % RP] = 0.0;
   __syncthreads();
   if (tid == 0)
     for (int j = 0; j < w; ++j) {
@@ -97,7 +110,7 @@ k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
     }
   __syncthreads();
   double* Tp = T + d.t_off + (int64_t)panel * RP * RP;
-  for (int e = tid; e < RP * RP; e += QNT) Tp[e] = Tl[e / RP][e % RP];
+  for (int e = tid; e < RP * RP; e += RPNT) Tp[e] = Tl[e / RP][e % RP];
 }
 
 // C <- (I - V op(T) V^T) C on rows [c0, M) of one instance, op(T) = T^T when
@@ -121,14 +134,15 @@ struct ApplyTarget {
 };
 
 // the apply's target for this workgroup, or false when it has nothing to do
+template <bool TW>
 __device__ __forceinline__ bool apply_target(const RedDesc& d, int panel, const double* W,
-                                             double* C, int target_w, ApplyTarget& a) {
+                                             double* C, ApplyTarget& a) {
   const int c0 = panel * RP;
   if (c0 >= d.kr) return false;
   a.w = min(RP, d.kr - c0);
   a.rows = d.M - c0;
   a.a0 = W + d.w_off + (int64_t)c0 * d.n + c0;
-  if (target_w) {
+  if (TW) {
     a.ncols = d.n - c0 - a.w;
     a.ld = d.n;
     a.cb = C + d.w_off + (int64_t)c0 * d.n + c0 + a.w;
@@ -152,12 +166,13 @@ __device__ __forceinline__ void stage_v(double (*Vs)[RP + 1], const ApplyTarget&
   }
 }
 
+template <bool TW>
 __global__ void __launch_bounds__(QNT)
 k_red_apply_z(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
-              double* __restrict__ C, double* __restrict__ Zp, int target_w) {
+              double* __restrict__ C, double* __restrict__ Zp) {
   const RedDesc d = descs[blockIdx.x];
   ApplyTarget a;
-  if (!apply_target(d, panel, W, C, target_w, a)) return;
+  if (!apply_target<TW>(d, panel, W, C, a)) return;
   __shared__ double Vs[RCH][RP + 1];
   const int col = blockIdx.y * QNT + threadIdx.x;
   const bool ok = col < a.ncols;
@@ -188,13 +203,14 @@ k_red_apply_z(const RedDesc* __restrict__ descs, int panel, const double* __rest
   }
 }
 
+template <bool TW>
 __global__ void __launch_bounds__(QNT)
 k_red_apply_c(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
               const double* __restrict__ T, double* __restrict__ C,
-              const double* __restrict__ Zp, int target_w, int trans) {
+              const double* __restrict__ Zp, int trans) {
   const RedDesc d = descs[blockIdx.x];
   ApplyTarget a;
-  if (!apply_target(d, panel, W, C, target_w, a)) return;
+  if (!apply_target<TW>(d, panel, W, C, a)) return;
   __shared__ double Ts[RP][RP + 1];
   __shared__ double Vs[RCH][RP + 1];
   const int tid = threadIdx.x;
@@ -349,7 +365,7 @@ k_red_tail(const RedDesc* __restrict__ descs, const double* __restrict__ Oinv,
 hipError_t launch_red_panel(const RedDesc* d, int B, int panel, double* W, double* tau,
                            double* T, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_red_panel, dim3(B), dim3(QNT), 0, s, d, panel, W, tau, T);
+  hipLaunchKernelGGL(k_red_panel, dim3(B), dim3(RPNT), 0, s, d, panel, W, tau, T);
   return hipGetLastError();
 }
 
@@ -358,10 +374,19 @@ hipError_t launch_red_apply(const RedDesc* d, int B, int panel, const double* W,
                            int maxcols, int maxrows, hipStream_t s) {
   if (B <= 0 || maxcols <= 0 || maxrows <= 0) return hipSuccess;
   const dim3 grid(B, (maxcols + QNT - 1) / QNT, (maxrows + RED_SEG - 1) / RED_SEG);
-  hipLaunchKernelGGL(k_red_apply_z, grid, dim3(QNT), 0, s, d, panel, W, C, Zp, target_w);
+  // separate instantiations for W and for the vectors: their shapes differ,
+  // and so do their durations in a kernel trace
+  if (target_w)
+    hipLaunchKernelGGL(k_red_apply_z<true>, grid, dim3(QNT), 0, s, d, panel, W, C, Zp);
+  else
+    hipLaunchKernelGGL(k_red_apply_z<false>, grid, dim3(QNT), 0, s, d, panel, W, C, Zp);
   if (hipError_t e = hipGetLastError()) return e;
-  hipLaunchKernelGGL(k_red_apply_c, grid, dim3(QNT), 0, s, d, panel, W, T, C,
-                     (const double*)Zp, target_w, trans);
+  if (target_w)
+    hipLaunchKernelGGL(k_red_apply_c<true>, grid, dim3(QNT), 0, s, d, panel, W, T, C,
+                       (const double*)Zp, trans);
+  else
+    hipLaunchKernelGGL(k_red_apply_c<false>, grid, dim3(QNT), 0, s, d, panel, W, T, C,
+                       (const double*)Zp, trans);
   return hipGetLastError();
 }
 
