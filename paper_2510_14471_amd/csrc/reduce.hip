@@ -122,8 +122,9 @@ k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
 //   k_red_apply_z   partial z_s = V_s^T c_s of the segment
 //   k_red_apply_c   z = sum of the partials (fixed order), z' = op(T) z,
 //                   c_s -= V_s z'
-// V is staged in LDS RCH rows at a time and RU rows of c are loaded before
-// they are used.
+// V is staged in LDS RCH rows at a time, unpadded: every lane reads the same
+// V entry (a broadcast), so rows 16-byte aligned give two entries per read;
+// RU rows of c are loaded before they are used.
 constexpr int RU = 32;
 static_assert(RED_SEG % RCH == 0 && RCH % RU == 0, "segment, chunk and batch sizes nest");
 
@@ -158,7 +159,7 @@ __device__ __forceinline__ bool apply_target(const RedDesc& d, int panel, const 
   return true;
 }
 
-__device__ __forceinline__ void stage_v(double (*Vs)[RP + 1], const ApplyTarget& a, int ldw,
+__device__ __forceinline__ void stage_v(double (*Vs)[RP], const ApplyTarget& a, int ldw,
                                         int r0) {
   for (int e = threadIdx.x; e < RCH * RP; e += QNT) {
     const int r = e / RP, j = e % RP;
@@ -173,7 +174,7 @@ k_red_apply_z(const RedDesc* __restrict__ descs, int panel, const double* __rest
   const RedDesc d = descs[blockIdx.x];
   ApplyTarget a;
   if (!apply_target<TW>(d, panel, W, C, a)) return;
-  __shared__ double Vs[RCH][RP + 1];
+  __shared__ __align__(16) double Vs[RCH][RP];
   const int col = blockIdx.y * QNT + threadIdx.x;
   const bool ok = col < a.ncols;
   const double* cc = a.cb + col;
@@ -212,7 +213,7 @@ k_red_apply_c(const RedDesc* __restrict__ descs, int panel, const double* __rest
   ApplyTarget a;
   if (!apply_target<TW>(d, panel, W, C, a)) return;
   __shared__ double Ts[RP][RP + 1];
-  __shared__ double Vs[RCH][RP + 1];
+  __shared__ __align__(16) double Vs[RCH][RP];
   const int tid = threadIdx.x;
   {
     const double* Tp = T + d.t_off + (int64_t)panel * RP * RP;
