@@ -419,6 +419,11 @@ namespace {
 struct RedPlan {
   int B = 0, maxpan = 0, maxn = 0, maxGK = 0, maxM = 0;
   std::vector<RedDesc> d;
+  // the device copy of the descriptors, tallest instance first: every
+  // reduction kernel takes its instance from its descriptor, so the order
+  // only sets the launch order, and the sequential panel kernel then
+  // schedules the longest jobs first
+  std::vector<RedDesc> d_dev;
   std::vector<int32_t> G, M, K, k, n;
   glm_shape sub{};
   int64_t sumMn = 0, sumMGK = 0, sumMrn = 0, sumMrGK = 0, sumn = 0, sumT = 0, sumG2 = 0,
@@ -478,6 +483,9 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     noff += d.G;
   }
   r.n.assign(s->n, s->n + noff);
+  r.d_dev = r.d;
+  std::stable_sort(r.d_dev.begin(), r.d_dev.end(),
+                   [](const RedDesc& a, const RedDesc& b) { return a.M > b.M; });
   r.sub.batch = r.B;
   r.sub.G = r.G.data();
   r.sub.M = r.M.data();
@@ -1002,7 +1010,7 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
   const RedDesc* dd = f->at<RedDesc>(r.o_desc);
   double* W = f->at<double>(r.o_W);
   double* T = f->at<double>(r.o_T);
-  hipError_t e = hipMemcpyAsync(f->ws + r.o_desc, r.d.data(), sizeof(RedDesc) * r.d.size(),
+  hipError_t e = hipMemcpyAsync(f->ws + r.o_desc, r.d_dev.data(), sizeof(RedDesc) * r.d_dev.size(),
                                 hipMemcpyHostToDevice, stream);
   if (!e) e = hipMemcpyAsync(W, X, 8 * r.sumMn, hipMemcpyDeviceToDevice, stream);
   for (int p = 0; p < r.maxpan && !e; ++p) {
