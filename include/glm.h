@@ -229,9 +229,10 @@ int glm_get_stats(const glm_factor* f, glm_stats* out);
  * the number of launches, their summed duration in milliseconds and the
  * summed algorithmic bytes; it then clears the counters.  On a GLM_REDUCED
  * handle ids 0 and 1 report the passes of the reduced solve and id 2 the
- * block-reflector applications of the reduction QR (target rows read and
- * written once plus the panel's reflectors read once); id 2 reads zero on
- * other handles. */
+ * block-reflector applications of glm_gls_solve (Q^T Y and Q Z; the target
+ * rows read and written once plus the panel's reflectors read once); the
+ * factorization runs before its handle exists and is not timed.  Id 2 reads
+ * zero on other handles. */
 int glm_profile_enable(glm_factor* f, int on);
 int glm_profile_read(glm_factor* f, int kernel_id, int64_t* launches,
                      double* total_ms, double* total_bytes);
