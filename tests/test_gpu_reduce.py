@@ -145,3 +145,16 @@ def test_reduced_repeated_intercepts(glmlib, precision):
     insts = list(synth.config2(subset=[12, 228]))
     out = run_reduced(glmlib, insts, precision, tol=1e-12)
     check_against_oracle(insts, out)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reduced_at_the_equation_limit(glmlib, precision):
+    """G = 64, the most equations the reduction takes (Omega^-1 and the
+    dropped rows' Z = (Q^T Y) Omega^-1 use 64 x 64 arrays in LDS), with W of
+    128 to 192 columns (four to six Householder panels) and rows in several
+    apply segments."""
+    insts = list(synth.small_batch(seed=181, B=2, G_rng=(64, 64), M_rng=(300, 1500),
+                                   n_rng=(2, 3), K_rng=(1, 3)))
+    assert all(i.G == 64 for i in insts)
+    out = run_reduced(glmlib, insts, precision)
+    check_against_oracle(insts, out)
