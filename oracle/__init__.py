@@ -9,9 +9,10 @@ Contents
   gls.py      closed-form / direct estimators (the definition of the result)
   pcg_aug.py  the PCG-Aug iteration in the paper's order and notation
               (FP64, and exact rational arithmetic for tiny integer data)
-  grad.py     dense reference gradients of the GLS estimator
-  fixtures.py script that writes stored expected values under tests/golden
+  grad.py     dense reference gradients of the GLS estimator (unrestricted
+              and restricted)
+  reduce.py   the SUR model reduction (QR of W = [X_1 ... X_G])
 
 Parity status of every function is stated in its docstring.
 """
-from . import gls, pcg_aug, grad  # noqa: F401
+from . import gls, pcg_aug, grad, reduce  # noqa: F401

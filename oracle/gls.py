@@ -49,11 +49,6 @@ def gls_dense(X, Sigma, y):
     return np.linalg.solve(X.T @ Si_X, X.T @ Si_y)
 
 
-def ols_dense(X, y):
-    """b_OLS = (X^T X)^-1 X^T y  (eq. OLS)."""
-    return np.linalg.solve(X.T @ X, X.T @ y)
-
-
 def augmented_matrix(X, Sigma, C=None):
     """Coefficient matrix of eq. aug1, or of eq. GRGLM when C is given."""
     m, n = X.shape

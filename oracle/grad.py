@@ -20,8 +20,23 @@ lambda_w = Sigma^-1 (g_w - X lambda_b).
 Symmetric convention: dOmega is returned symmetric, with dL = <dOmega, E>_F
 for every symmetric perturbation E.
 
+With restrictions R_c b = r (eq. GRGLM: the restriction rows are extra
+observations of zero variance), x = [w; w_c; b] and the same rule holds:
+A = [[Sigmabar, Xbar], [Xbar^T, 0]] with Xbar = [X; R_c], Sigmabar =
+diag(Sigma, 0).  Sigma and X enter A exactly as before, so dL/dy, dL/dOmega
+and dL/dX keep the formulas above with the restricted solution (w, b) and
+the restricted adjoint (lambda_w, lambda_b); the adjoint of nonsingular
+Omega is the (n + k) x (n + k) KKT system
+
+    [ X^T Sigma^-1 X   -R_c^T ] [lambda_b]   [ X^T Sigma^-1 g_w - g_b ]
+    [ R_c                0    ] [lambda_c] = [ 0                      ],
+
+lambda_w = Sigma^-1 (g_w - X lambda_b)   (the first rows of A lambda = g and
+its restriction rows R_c lambda_b = 0).
+
 Parity status: pinned against central finite differences of the direct
-estimator (tests/test_oracle_pins.py).
+estimators, and the restricted adjoint against the dense augmented system
+(tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 
@@ -54,6 +69,43 @@ def sur_gls_vjp(inst, beta, U, g_beta, g_u=None):
         dW[:, o:o + ni] = -(lam_w[:, i, :] @ beta[o:o + ni, :].T
                             + U[:, i, :] @ lam_b[o:o + ni, :].T)
     return dY, dOmega, dW
+
+
+def _grads_from_adjoint(inst, beta, U, lam_w, lam_b):
+    """dY, dOmega (symmetric), dW from the solution (U, beta) and the adjoint."""
+    S = np.einsum("tik,tjk->ij", lam_w, U)
+    dOmega = -0.5 * (S + S.T)
+    dW = np.empty_like(inst.W)
+    for i in range(inst.G):
+        o, ni = inst.col_off[i], inst.n_i[i]
+        dW[:, o:o + ni] = -(lam_w[:, i, :] @ beta[o:o + ni, :].T
+                            + U[:, i, :] @ lam_b[o:o + ni, :].T)
+    return lam_w, dOmega, dW
+
+
+def restricted_gls_vjp(inst, beta, U, g_beta, g_u=None):
+    """Vector-Jacobian product of the restricted GLS solution (beta, U) of
+    eq. GRGLM (nonsingular Omega, R_c of full row rank) for all K right-hand
+    sides, through the KKT form of the adjoint system in the module
+    docstring.  Returns (dY M x G x K, dOmega G x G, dW M x n); the
+    gradients w.r.t. R_c and r are not formed."""
+    G, K, n, kc = inst.G, inst.K, inst.n, inst.kc
+    Oinv = sla.cho_solve(sla.cho_factor(inst.Omega), np.eye(G))
+    WtW, WtY = _cross_products(inst)
+    A, _ = _kron_weighted(inst, WtW, WtY, Oinv)
+    if g_u is None:
+        g_u = np.zeros_like(inst.Y)
+    Gs = np.einsum("tik,ij->tjk", g_u, Oinv)
+    XtSg = np.concatenate([inst.X(i).T @ Gs[:, i, :] for i in range(G)], 0)
+    kkt = np.zeros((n + kc, n + kc))
+    kkt[:n, :n] = A
+    kkt[:n, n:] = -inst.Rc.T
+    kkt[n:, :n] = inst.Rc
+    rhs = np.zeros((n + kc, K))
+    rhs[:n] = XtSg - g_beta
+    lam_b = np.linalg.solve(kkt, rhs)[:n]
+    lam_w = np.einsum("tik,ij->tjk", g_u - fitted(inst, lam_b), Oinv)
+    return _grads_from_adjoint(inst, beta, U, lam_w, lam_b)
 
 
 def nll_omega(inst, beta):

@@ -2,19 +2,23 @@
 
 This is Algorithm "The PCG-Aug method" (alg. glmpcg2) applied to the
 augmented system of eq. aug1 with the indefinite preconditioner of
-eq. invprec / eq. prec, where the auxiliary matrix is D = alpha I:
+eq. invprec / eq. prec.  The auxiliary matrix D is either alpha I or, for a
+SUR model, one scalar per equation, D = diag(d_1..d_G) (x) I_M (the VAR
+experiments use both: D_1 = alpha I and D_2 = diag Sigma).  For a SUR model
+X is block diagonal, so in both cases
 
-    X* = D^-1 X (X^T D^-1 X)^-1 = X (X^T X)^-1,
-    Pi = (I - X* X^T) D^-1        = (I - X (X^T X)^-1 X^T) / alpha,
+    X* = D^-1 X (X^T D^-1 X)^-1 = X (X^T X)^-1          (D cancels blockwise),
+    Pi = (I - X* X^T) D^-1,  block i:  (I - X_i (X_i^T X_i)^-1 X_i^T) / d_i,
 
-so that X*^T r and Pi r are the OLS estimate and residual (scaled by
-1/alpha) of an auxiliary regression of r on X (the "auxiliary GLM").
-For SUR models (SUR section) both operators act block by block through
-thin QR factors X_i = Q_i R_i:  X_i*^T xi = R_i^-1 Q_i^T xi,
-Pi_i xi = (xi - Q_i Q_i^T xi) / alpha, and Sigma u = vec(U Omega).
+so that X*^T r and Pi r are the OLS estimate and the residual (scaled by
+1/d_i) of an auxiliary regression of r on X (the "auxiliary GLM").
+Both operators act block by block through thin QR factors X_i = Q_i R_i:
+X_i*^T xi = R_i^-1 Q_i^T xi, Pi_i xi = (xi - Q_i Q_i^T xi) / d_i, and
+Sigma u = vec(U Omega).
 With restrictions (restricted GLM section) the restrictions are k extra
 observations of zero variance: Xbar = [X; R_c], Sigmabar = diag(Sigma, 0),
-D = alpha I_{m+k}, and X*, Pi follow eq. rglm1m.
+D = alpha I_{m+k}, and X*, Pi follow eq. rglm1m (the per-equation D is
+offered for unrestricted instances only).
 
 Iterates kept exactly as in the algorithm: residual r, search direction
 blocks u (w-space) and v (z-space), scalars c, d, lambda, mu; the
@@ -48,12 +52,21 @@ class SurOperators:
     Vectors in observation space are flat: vec(U) (equation-major, length
     G*M) followed by the k restriction entries."""
 
-    def __init__(self, inst, alpha: float):
+    def __init__(self, inst, alpha):
         self.inst = inst
-        self.alpha = float(alpha)
         self.M, self.G, self.n = inst.M, inst.G, inst.n
         self.kc = inst.kc
         self.m = self.G * self.M + self.kc
+        d = np.asarray(alpha, dtype=np.float64)
+        if d.ndim == 0:
+            d = np.full(self.G, float(d))
+        if d.shape != (self.G,) or not np.all(d > 0):
+            raise ValueError("D needs one positive scalar, or one per equation")
+        if self.kc and not np.all(d == d[0]):
+            raise ValueError("restricted instances take D = alpha I")
+        self.d = d
+        # the diagonal of D over the observation space (restriction rows: d_1)
+        self.Ddiag = np.concatenate([np.repeat(d, self.M), np.full(self.kc, d[0])])
         self.QR = [np.linalg.qr(inst.X(i)) for i in range(self.G)]
         if self.kc:
             # X^T X + R_c^T R_c (the D's cancel when D_Z = D_C = alpha I)
@@ -107,7 +120,11 @@ class SurOperators:
         return self.pack(np.column_stack(cols))
 
     def Pi(self, xi):
-        return (xi - self.X(self.Xstar_T(xi))) / self.alpha
+        return (xi - self.X(self.Xstar_T(xi))) / self.Ddiag
+
+    def Dnorm2(self, g):
+        """g^T D g, which equals r^T Pi r for g = Pi r (Pi D Pi = Pi)."""
+        return float(g @ (self.Ddiag * g))
 
 
 @dataclass
@@ -127,16 +144,23 @@ def default_alpha(Omega):
     return float(np.max(np.diag(Omega)))
 
 
+def per_equation_d(Omega):
+    """D = diag(omega_11 .. omega_GG) (x) I_M, the SUR form of D_2 = diag Sigma."""
+    return np.array(np.diag(Omega), dtype=np.float64)
+
+
 def pcg_aug(inst, k: int = 0, tol: float = 1e-12, max_iter: Optional[int] = None,
             alpha: Optional[float] = None, y=None, h2=None, stall: int = 20,
             keep_w: bool = False) -> PcgResult:
     """Algorithm glmpcg2 for right-hand side k of a SUR instance.
 
     ``y`` overrides the observation vector (flat, length G*M+k) and ``h2``
-    gives a nonzero lower right-hand side.  Stops when sqrt(c_{i+1}/c_1) <= tol
-    ("small enough"), when c has not reached a new minimum for ``stall``
-    iterations ("not anymore able to decrease"), on breakdown (d <= 0 or not
-    finite) or after max_iter = m - n + 1 iterations."""
+    gives a nonzero lower right-hand side; ``alpha`` is the scalar of
+    D = alpha I or a length-G vector (D = diag(d) (x) I_M).  The stopping
+    rule of the algorithm is read as: stop once sqrt(c_{i+1}/c_1) <= tol, or
+    once c has gone ``stall`` iterations without a new minimum (no further
+    progress is possible in floating point), on breakdown (d <= 0 or not
+    finite), or after max_iter = m - n + 1 iterations."""
     a = default_alpha(inst.Omega) if alpha is None else alpha
     ops = SurOperators(inst, a)
     if y is None:
@@ -208,7 +232,8 @@ def pcg_aug_projected(inst, k: int = 0, tol: float = 1e-12,
 
     Two identities stated next to eq. Xstar make this the same iteration:
     Pi X = 0 removes the X v_i term from  Pi r_{i+1} = Pi r_i - lambda_i Pi (Sigma u_i
-    + X v_i), and Pi D Pi = Pi gives  c_i = r_i^T Pi r_i = alpha ||g_i||^2.  The
+    + X v_i), and Pi D Pi = Pi gives  c_i = r_i^T Pi r_i = g_i^T D g_i
+    (alpha ||g_i||^2 for D = alpha I).  The
     z-direction v_i is then unused (the estimate is recovered from w at
     termination exactly as in the algorithm), so it is not carried.  In
     exact arithmetic every iterate (w_i, u_i, c_i, d_i, lambda_i, mu_i)
@@ -229,7 +254,7 @@ def pcg_aug_projected(inst, k: int = 0, tol: float = 1e-12,
         max_iter = m - n + 1
     w = ops.Xstar(h2) if h2 is not None else np.zeros(m)
     g = ops.Pi(ops.Sigma(w) - y)          # z_1 = 0
-    c = a * float(g @ g)
+    c = ops.Dnorm2(g)
     c1 = c
     u = np.zeros(m)
     mu = 0.0
@@ -258,7 +283,7 @@ def pcg_aug_projected(inst, k: int = 0, tol: float = 1e-12,
         if keep_w:
             res.w_iterates.append(w.copy())
         g = g - lam * ops.Pi(Su)
-        c_new = a * float(g @ g)
+        c_new = ops.Dnorm2(g)
         res.c.append(c_new)
         if np.sqrt(c_new / c1) <= tol:
             res.status = "converged"
@@ -276,18 +301,6 @@ def pcg_aug_projected(inst, k: int = 0, tol: float = 1e-12,
     res.z_hat = ops.Xstar_T(y - ops.Sigma(w))
     res.w = w
     return res
-
-
-def pcg_aug_sur(inst, tol=1e-12, projected=True, **kw):
-    """PCG-Aug over every right-hand side: (beta n x K, U M x G x K, results)."""
-    fn = pcg_aug_projected if projected else pcg_aug
-    betas, Us, results = [], [], []
-    for k in range(inst.K):
-        res = fn(inst, k=k, tol=tol, **kw)
-        betas.append(res.z_hat)
-        Us.append(res.w[: inst.G * inst.M].reshape(inst.G, inst.M).T)
-        results.append(res)
-    return np.stack(betas, 1), np.stack(Us, 2), results
 
 
 # --------------------------------------------------------------------------

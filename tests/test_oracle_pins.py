@@ -513,3 +513,130 @@ def test_model_reduction_drops_only_noise_rows():
     Z[:red.M] = Ur
     U_no_tail = np.einsum("ts,sik->tik", Q, Z)
     assert rel_err(U_no_tail, U_d) > 1e-2
+
+
+# -- restricted gradients: FD of the restricted estimator, dense adjoint --------
+
+def _restricted_fd_instance():
+    return synth.small_batch(seed=67, B=1, G_rng=(3, 3), M_rng=(20, 20),
+                             n_rng=(2, 3), K_rng=(1, 1), shift=0.5, constraints=2)[0]
+
+
+def _perturbed_keep_rc(inst, what, idx, h):
+    out = _perturbed(inst, what, idx, h)
+    out.Rc, out.r = inst.Rc, inst.r
+    return out
+
+
+def test_restricted_vjp_matches_fd_and_dense_adjoint():
+    inst = _restricted_fd_instance()
+    rng = np.random.default_rng(3)
+    gb = rng.standard_normal((inst.n, 1))
+    gu = rng.standard_normal(inst.Y.shape)
+
+    def loss(I):
+        beta, U, _ = gls.restricted_gls(I)
+        return float(np.sum(gb * beta) + np.sum(gu * U))
+
+    beta, U, wc = gls.restricted_gls(inst)
+    grads = grad.restricted_gls_vjp(inst, beta, U, gb, gu)
+    coords = _coords(inst, rng, count=40)
+    for what, idx in coords:
+        fd = (loss(_perturbed_keep_rc(inst, what, idx, 1e-6)) -
+              loss(_perturbed_keep_rc(inst, what, idx, -1e-6))) / 2e-6
+        dY, dOm, dW = grads
+        an = dY[idx] if what == "Y" else dW[idx] if what == "W" else \
+            dOm[idx] * (1 if idx[0] == idx[1] else 2)
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-7, (what, idx, fd, an)
+    # the adjoint of the dense restricted augmented system (eq. GRGLM):
+    # A [l_w; l_c; l_b] = [g_u; 0; g_b], solved by least squares
+    X, S, _ = gls.sur_dense(inst, 0)
+    lw, lb = gls.augmented_lstsq(X, S, gu[:, :, 0].T.reshape(-1), inst.Rc,
+                                 np.zeros(inst.kc), h2=gb[:, 0])
+    m = X.shape[0]
+    dY = grads[0][:, :, 0].T.reshape(-1)
+    assert rel_err(dY, lw[:m]) < 1e-9
+    w = U[:, :, 0].T.reshape(-1)
+    dX_dense = -(np.outer(lw[:m], beta[:, 0]) + np.outer(w, lb))
+    dW = np.concatenate([dX_dense[i * inst.M:(i + 1) * inst.M,
+                                  inst.col_off[i]:inst.col_off[i] + inst.n_i[i]]
+                         for i in range(inst.G)], 1)
+    assert rel_err(grads[2], dW) < 1e-9
+
+
+def test_planted_mistake_unrestricted_adjoint_on_restricted_problem_is_caught():
+    """The unrestricted adjoint (no KKT rows) is wrong for a restricted
+    solution; the finite-difference pin sees it."""
+    inst = _restricted_fd_instance()
+    rng = np.random.default_rng(4)
+    gb = rng.standard_normal((inst.n, 1))
+
+    def loss(I):
+        return float(np.sum(gb * gls.restricted_gls(I)[0]))
+
+    beta, U, _ = gls.restricted_gls(inst)
+    wrong = grad.sur_gls_vjp(inst, beta, U, gb)
+    bad = 0
+    for what, idx in _coords(inst, rng, count=30):
+        fd = (loss(_perturbed_keep_rc(inst, what, idx, 1e-6)) -
+              loss(_perturbed_keep_rc(inst, what, idx, -1e-6))) / 2e-6
+        dY, dOm, dW = wrong
+        an = dY[idx] if what == "Y" else dW[idx] if what == "W" else \
+            dOm[idx] * (1 if idx[0] == idx[1] else 2)
+        bad += abs(fd - an) > 1e-6 * abs(an) + 1e-7
+    assert bad > 0
+
+
+# -- per-equation preconditioner D = diag(d) (x) I_M ------------------------------
+
+def test_per_equation_d_diagonal_omega_terminates_in_one_step():
+    """With Sigma = D the preconditioner K is the exact inverse of the
+    augmented matrix (eq. invprec / eq. prec), so PCG-Aug ends after one
+    step, at blockwise OLS; D = alpha I needs one step per distinct
+    omega_ii instead."""
+    inst = synth.small_batch(seed=5, B=1, G_rng=(3, 3), M_rng=(50, 50),
+                             n_rng=(2, 4), K_rng=(2, 2))[0]
+    inst.Omega = np.diag([0.7, 1.9, 3.1])
+    ols = _blockwise_ols(inst)
+    for k in range(inst.K):
+        res = pcg_aug.pcg_aug(inst, k=k, tol=1e-13, alpha=pcg_aug.per_equation_d(inst.Omega))
+        assert res.status == "converged" and res.iterations == 1, res.iterations
+        assert rel_err(res.z_hat, ols[:, k]) < 1e-12
+        resp = pcg_aug.pcg_aug_projected(inst, k=k, tol=1e-13,
+                                         alpha=pcg_aug.per_equation_d(inst.Omega))
+        assert resp.iterations == 1 and rel_err(resp.z_hat, ols[:, k]) < 1e-12
+        res_a = pcg_aug.pcg_aug(inst, k=k, tol=1e-13)
+        assert res_a.iterations == inst.G
+
+
+def test_per_equation_d_leaves_beta_unchanged():
+    """beta does not depend on D (X* is D-free for block-diagonal X)."""
+    for inst in _nonsingular_batch()[:3]:
+        beta, U = gls.sur_gls(inst)
+        d = pcg_aug.per_equation_d(inst.Omega)
+        for k in range(inst.K):
+            res = pcg_aug.pcg_aug_projected(inst, k=k, tol=1e-13, alpha=d)
+            assert rel_err(res.z_hat, beta[:, k]) < 1e-10
+            assert rel_err(res.w, U[:, :, k].T.reshape(-1)) < 1e-9
+
+
+def test_planted_mistake_scalar_norm_with_per_equation_d_is_caught():
+    """c = alpha ||Pi r||^2 is right only for D = alpha I; with a per-equation
+    D the projected form must use g^T D g.  Using the scalar form breaks
+    the one-step termination of the diagonal case."""
+    inst = synth.small_batch(seed=5, B=1, G_rng=(3, 3), M_rng=(50, 50),
+                             n_rng=(2, 4), K_rng=(1, 1))[0]
+    inst.Omega = np.diag([0.7, 1.9, 3.1])
+    d = pcg_aug.per_equation_d(inst.Omega)
+    ops = pcg_aug.SurOperators(inst, d)
+    y = ops.pack(inst.Y[:, :, 0])
+    g = ops.Pi(-y)
+    c_right = ops.Dnorm2(g)
+    c_wrong = float(d.max() * (g @ g))
+    u = g
+    lam_right = c_right / float(u @ ops.Sigma(u))
+    lam_wrong = c_wrong / float(u @ ops.Sigma(u))
+    g1 = g - lam_right * ops.Pi(ops.Sigma(u))
+    g1w = g - lam_wrong * ops.Pi(ops.Sigma(u))
+    assert np.linalg.norm(g1) < 1e-12 * np.linalg.norm(g)
+    assert np.linalg.norm(g1w) > 1e-3 * np.linalg.norm(g)
