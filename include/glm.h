@@ -114,6 +114,16 @@ typedef struct glm_stats {
   int64_t pcg_iterations;     /* sum over (instance, rhs) of PCG iterations       */
   int32_t max_iterations;     /* largest per-(instance, rhs) PCG iteration count  */
   int32_t launches;           /* kernel launches enqueued by the call            */
+  /* Projection-pass configuration chosen for the handle's shape.  Index 0:
+     the single-precision inner solves (GLM_MIXED; -1 on GLM_FP64 handles),
+     index 1: the double-precision solves.                                  */
+  int32_t pass_rowvec[2];     /* 1 row-vector passes, 0 column-slot passes     */
+  int32_t pass_kv[2];         /* right-hand sides per lane (row-vector passes) */
+  int32_t pass_ks[2];         /* 16: the sixteen-rhs specialisation, else 0    */
+  int32_t pass_omega[2];      /* Omega apply of the row-vector passes: -16, -32
+                                 or -64 on the matrix cores (G padded to that
+                                 size), 32 from registers, 0 from LDS         */
+  int32_t pass_nim[2];        /* widest block, rounded up to 8, 16, 24, 32, 64 */
 } glm_stats;
 
 /* Bytes of device workspace needed by glm_qr_factor / glm_gls_solve /
@@ -217,6 +227,13 @@ int glm_gls_backward(glm_factor* f, const double* Omega,
  * convention (R_jj may be negative).  GLM_OK or GLM_EINVAL / GLM_EHIP. */
 int glm_copy_factors(const glm_factor* f, double* Q, double* R, int32_t* rank,
                      hipStream_t stream);
+
+/* Host only (no device call): the projection-pass configuration that
+ * glm_qr_factor chooses for this shape and precision, in the pass_* fields
+ * of `out` (the counters are zeroed).  With GLM_REDUCED it is the
+ * configuration of the reduced problem's solve.  GLM_OK, GLM_EINVAL or
+ * GLM_EUNSUPPORTED (as glm_validate_shape). */
+int glm_plan_passes(const glm_shape* shape, glm_precision prec, glm_stats* out);
 
 /* Counters of the last solve/backward on the handle.  GLM_OK or GLM_EINVAL. */
 int glm_get_stats(const glm_factor* f, glm_stats* out);

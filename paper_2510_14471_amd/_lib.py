@@ -39,7 +39,10 @@ class GlmShape(ctypes.Structure):
 
 class GlmStats(ctypes.Structure):
     _fields_ = [("outer_steps", c_int32), ("pcg_iterations", c_int64),
-                ("max_iterations", c_int32), ("launches", c_int32)]
+                ("max_iterations", c_int32), ("launches", c_int32),
+                ("pass_rowvec", c_int32 * 2), ("pass_kv", c_int32 * 2),
+                ("pass_ks", c_int32 * 2), ("pass_omega", c_int32 * 2),
+                ("pass_nim", c_int32 * 2)]
 
 
 class GLMError(RuntimeError):
@@ -66,6 +69,8 @@ def _load():
     lib.glm_gls_backward.restype = c_int
     lib.glm_copy_factors.argtypes = [P, P, P, P, P]
     lib.glm_copy_factors.restype = c_int
+    lib.glm_plan_passes.argtypes = [POINTER(GlmShape), c_int, POINTER(GlmStats)]
+    lib.glm_plan_passes.restype = c_int
     lib.glm_get_stats.argtypes = [P, POINTER(GlmStats)]
     lib.glm_get_stats.restype = c_int
     lib.glm_profile_enable.argtypes = [P, c_int]
@@ -83,8 +88,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["glm_validate_shape", "glm_workspace_bytes", "glm_qr_factor", "glm_gls_solve",
-            "glm_gls_backward", "glm_copy_factors", "glm_get_stats", "glm_profile_enable", "glm_profile_read",
-            "glm_factor_destroy", "glm_strerror"]
+            "glm_gls_backward", "glm_copy_factors", "glm_plan_passes", "glm_get_stats",
+            "glm_profile_enable", "glm_profile_read", "glm_factor_destroy", "glm_strerror"]
 
 
 def glm_strerror(code: int) -> str:
@@ -169,11 +174,30 @@ def glm_copy_factors(h, Q, R, rank, stream=None) -> int:
     return rc
 
 
+def _passes(st) -> dict:
+    # pass configuration per precision: keys "fp32" (inner solves) and "fp64"
+    out = {}
+    for pi, name in enumerate(("fp32", "fp64")):
+        out[name + "_passes"] = {"rowvec": st.pass_rowvec[pi], "kv": st.pass_kv[pi],
+                                 "ks": st.pass_ks[pi], "omega": st.pass_omega[pi],
+                                 "nim": st.pass_nim[pi]}
+    return out
+
+
+def glm_plan_passes(shape: Shape, precision: int) -> dict:
+    st = GlmStats()
+    _check(_lib.glm_plan_passes(shape.ptr(), int(precision), ctypes.byref(st)),
+           "glm_plan_passes")
+    return _passes(st)
+
+
 def glm_get_stats(h) -> dict:
     st = GlmStats()
     _check(_lib.glm_get_stats(h, ctypes.byref(st)), "glm_get_stats")
-    return {"outer_steps": st.outer_steps, "pcg_iterations": st.pcg_iterations,
-            "max_iterations": st.max_iterations, "launches": st.launches}
+    out = {"outer_steps": st.outer_steps, "pcg_iterations": st.pcg_iterations,
+           "max_iterations": st.max_iterations, "launches": st.launches}
+    out.update(_passes(st))
+    return out
 
 
 def glm_profile_enable(h, on: bool):

@@ -409,6 +409,20 @@ struct EventPair {
   int kid;
 };
 
+// The pass configuration of a plan in the glm_stats fields (index 0: FP32
+// inner solves of the mixed path, -1 when there are none; 1: FP64 solves).
+void pass_stats(const Plan& p, glm_stats* st) {
+  for (int pi = 0; pi < 2; ++pi) {
+    const PassCfg& c = p.cfg[pi];
+    const bool used = pi == 1 || p.prec == GLM_MIXED;
+    st->pass_rowvec[pi] = used ? c.rowpass : -1;
+    st->pass_kv[pi] = used ? c.kv : -1;
+    st->pass_ks[pi] = used ? c.ks : -1;
+    st->pass_omega[pi] = used ? c.gr : -1;
+    st->pass_nim[pi] = used ? c.nim : -1;
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -807,6 +821,7 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
   f->launches = 0;
   f->stats = glm_stats{};
   const bool mixed = p.prec == GLM_MIXED;
+  pass_stats(p, &f->stats);
   GLM_CHECK(launch_alpha(f->d_inst(), p.B, Om, f->at<double>(p.o_alpha),
                          mixed ? f->at<float>(p.o_Om32) : nullptr, s));
   GLM_CHECK(launch_state_init(f->d_inst(), p.B, f->at<int>(p.o_flags), p.nblk,
@@ -1195,6 +1210,23 @@ int glm_copy_factors(const glm_factor* f, double* Q, double* R, int32_t* rank,
   if (rank)
     GLM_CHECK(hipMemcpyAsync(rank, f->ws + p.o_flags, 4 * (size_t)p.nblk,
                              hipMemcpyDeviceToDevice, stream));
+  return GLM_OK;
+}
+
+int glm_plan_passes(const glm_shape* shape, glm_precision prec, glm_stats* out) {
+  if (!out) return GLM_EINVAL;
+  *out = glm_stats{};
+  const glm_precision base = (glm_precision)((int)prec & ~GLM_REDUCED);
+  if (base != GLM_FP64 && base != GLM_MIXED) return GLM_EINVAL;
+  Plan p;
+  if ((int)prec & GLM_REDUCED) {
+    RedPlan r;
+    if (int rc = make_red_plan(shape, base, r)) return rc;
+    if (int rc = make_plan(&r.sub, base, p)) return rc;
+  } else if (int rc = make_plan(shape, base, p)) {
+    return rc;
+  }
+  pass_stats(p, out);
   return GLM_OK;
 }
 

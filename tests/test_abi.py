@@ -147,3 +147,26 @@ def test_reduction_needs_at_most_64_equations():
     s = _shape([65], [200], [1], [1] * 65)
     assert _lib.glm_workspace_bytes(s, _lib.GLM_FP64) > 0
     assert _lib.glm_workspace_bytes(s, _lib.GLM_FP64 | _lib.GLM_REDUCED) == 0
+
+
+@pytest.mark.parametrize("name", sorted(__import__("pass_cases").CASES))
+def test_pass_configuration_of_each_parity_case(name):
+    """The host-side planner selects, for each batch of the pass-configuration
+    parity tests, the configuration that test is meant to reach (so every
+    configuration is run on the GPU by some test)."""
+    import pass_cases
+    from paper_2510_14471_amd import _lib, BatchLayout
+    insts = pass_cases.instances(name)
+    _, want32, want64, reduced = pass_cases.CASES[name]
+    shape = BatchLayout.of(insts).shape()
+    precs = [(_lib.GLM_MIXED, True), (_lib.GLM_FP64, False)]
+    if reduced:
+        precs += [(_lib.GLM_MIXED | _lib.GLM_REDUCED, True),
+                  (_lib.GLM_FP64 | _lib.GLM_REDUCED, False)]
+    for prec, mixed in precs:
+        got = _lib.glm_plan_passes(shape, prec)
+        assert pass_cases.matches(got["fp64_passes"], want64), (prec, got)
+        if mixed:
+            assert pass_cases.matches(got["fp32_passes"], want32), (prec, got)
+        else:
+            assert got["fp32_passes"]["rowvec"] == -1, got
