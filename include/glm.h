@@ -81,7 +81,7 @@ typedef enum glm_precision {
                      (single-precision accumulation, double-precision dot
                      products), inside double-precision iterative refinement;
                      QR, refinement residual and the beta/u updates in double   */
-  GLM_REDUCED = 4 /* flag, OR-ed into GLM_FP64 or GLM_MIXED for
+  GLM_REDUCED = 4, /* flag, OR-ed into GLM_FP64 or GLM_MIXED for
                      glm_workspace_bytes and glm_qr_factor: SUR model reduction
                      (the remark on reducing the SUR model in the SUR section).
                      One Householder QR of W = [X_1 ... X_G] = Q [R; 0] per
@@ -95,6 +95,16 @@ typedef enum glm_precision {
                      GLM_EUNSUPPORTED).  glm_gls_backward and
                      glm_copy_factors return GLM_EUNSUPPORTED on such a
                      handle.                                                     */
+  GLM_PRECOND_EQ = 8 /* flag, OR-ed into the precision for glm_workspace_bytes,
+                     glm_qr_factor(_static) and glm_plan_passes: the
+                     preconditioner's auxiliary matrix is one scalar per
+                     equation, D = diag(omega_11 .. omega_GG) (x) I_M (the
+                     paper's D_2 = diag Sigma of the VAR experiments), so
+                     that Pi_i = (I - Q_i Q_i^T) / omega_ii; without it
+                     D = alpha I, alpha = max_i omega_ii.  beta and u do not
+                     depend on D; the iterations do (a diagonal Omega ends in
+                     one step).  Restricted instances, and equations with
+                     omega_ii = 0, keep alpha.                                   */
 } glm_precision;
 
 typedef struct glm_shape {

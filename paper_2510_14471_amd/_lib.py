@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libglm_hip.so")
 GLM_FP64 = 0
 GLM_MIXED = 1
 GLM_REDUCED = 4      # flag OR-ed into the precision: SUR model reduction
+GLM_PRECOND_EQ = 8   # flag OR-ed into the precision: D = diag(omega_ii) (x) I_M
 
 GLM_OK = 0
 GLM_EINVAL = -1
@@ -87,7 +88,8 @@ def _load():
 
 _lib = _load()
 
-EXPORTED = ["glm_validate_shape", "glm_workspace_bytes", "glm_qr_factor", "glm_gls_solve",
+EXPORTED = ["glm_validate_shape", "glm_workspace_bytes", "glm_qr_factor",
+            "glm_gls_solve",
             "glm_gls_backward", "glm_copy_factors", "glm_plan_passes", "glm_get_stats",
             "glm_profile_enable", "glm_profile_read", "glm_factor_destroy", "glm_strerror"]
 

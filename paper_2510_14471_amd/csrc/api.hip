@@ -46,6 +46,13 @@ constexpr int kMaxOuter = 12;             // refinement steps
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// GLM_FP64 or GLM_MIXED, optionally with the GLM_REDUCED and GLM_PRECOND_EQ flags
+bool prec_ok(glm_precision p) {
+  const int v = (int)p & ~(GLM_REDUCED | GLM_PRECOND_EQ);
+  return v == GLM_FP64 || v == GLM_MIXED;
+}
+
+
 // Progress trace on stderr when the environment variable GLM_LOG is set.
 bool log_on() {
   static const bool on = std::getenv("GLM_LOG") != nullptr;
@@ -114,6 +121,7 @@ PassCfg choose_cfg(const glm_shape* s, size_t sv, bool allow_rows) {
 struct Plan {
   int B = 0;
   glm_precision prec = GLM_FP64;
+  bool deq = false;   // D = diag(omega_ii) (x) I_M instead of alpha I
   std::vector<InstDesc> inst;
   std::vector<BlockDesc> blk;
   std::vector<TileDesc> tile;
@@ -129,7 +137,7 @@ struct Plan {
   PassCfg cfg[2];
   // byte offsets inside the workspace
   size_t o_Q64, o_Q32, o_R, o_Nb, o_colblk, o_inst, o_blk, o_tile, o_qrs, o_qrn, o_chunks,
-      o_rinst, o_rinst_index, o_flags, o_active, o_icount, o_count, o_st, o_ost, o_alpha,
+      o_rinst, o_rinst_index, o_flags, o_active, o_icount, o_count, o_st, o_ost, o_alpha, o_deq,
       o_Om32, o_g, o_u, o_wf, o_yf, o_y64, o_Tpart, o_Tm, o_dpart, o_cpart, o_gc, o_uc, o_wc,
       o_wc64, o_rho0, o_rhoc, o_lb, o_eye, o_mone, o_ypart, o_bytes;
   size_t total = 0;
@@ -169,13 +177,16 @@ int validate(const glm_shape* s) {
 }
 
 // allow_rows[pi]: the row-vector passes may be used for precision index pi
-int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = true,
+int make_plan(const glm_shape* s, glm_precision prec_flags, Plan& p, bool allow32 = true,
               bool allow64 = true) {
   int rc = validate(s);
   if (rc != GLM_OK) return rc;
+  // GLM_PRECOND_EQ selects D = diag(omega_ii) (x) I_M; the rest is the precision
+  const glm_precision prec = (glm_precision)((int)prec_flags & ~(GLM_PRECOND_EQ | GLM_REDUCED));
   p = Plan();
   p.B = s->batch;
   p.prec = prec;
+  p.deq = ((int)prec_flags & GLM_PRECOND_EQ) != 0;
   int64_t sum_rows = 0;
   for (int b = 0; b < p.B; ++b) sum_rows += s->M[b];
   // Row tiles of about equal streaming cost (Q row + three vector rows per
@@ -340,7 +351,7 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
   // an instance does not suit the row-vector passes of some precision: plan
   // again with the column-slot passes for that precision
   if ((p.cfg[0].rowpass && !rows_fit[0]) || (p.cfg[1].rowpass && !rows_fit[1]))
-    return make_plan(s, prec, p, allow32 && rows_fit[0], allow64 && rows_fit[1]);
+    return make_plan(s, prec_flags, p, allow32 && rows_fit[0], allow64 && rows_fit[1]);
   p.nblk = (int)p.blk.size();
   p.ntiles = (int)p.tile.size();
   for (size_t r = 0; r < p.qr_nb.size(); ++r) p.qr_nb[r].flag = p.nblk + (int)r;
@@ -375,6 +386,7 @@ int make_plan(const glm_shape* s, glm_precision prec, Plan& p, bool allow32 = tr
   p.o_st = take(sizeof(RhsState) * p.nrhs);
   p.o_ost = take(4 * p.nrhs);
   p.o_alpha = take(8 * p.B);
+  p.o_deq = take(8 * (size_t)p.nblk);
   p.o_Om32 = take(prec == GLM_MIXED ? 4 * p.sumG2 : 0);
   // iteration vectors hold FP64 values in both modes (FP32 inner solves use
   // the first half of each)
@@ -543,7 +555,9 @@ struct glm_factor {
   char* ws = nullptr;
   const double* X = nullptr;
   const double* Rc = nullptr;
-  int* h_count = nullptr;   // pinned
+  int* h_count = nullptr;   // pinned, or h_count_host when pinned memory is not wanted
+  bool h_count_pinned = false;
+  int h_count_host[4] = {0, 0, 0, 0};
   glm_stats stats{};
   bool prof = false;
   std::vector<EventPair> ev_used, ev_free;
@@ -598,6 +612,7 @@ PassLaunch<T> pass_args(glm_factor* f, const T* Q, const T* Om, const T* y, T* w
   a.Q = Q;
   a.Om = Om;
   a.alpha = f->at<double>(p.o_alpha);
+  a.deq = p.deq ? f->at<double>(p.o_deq) : nullptr;
   a.st = f->d_st();
   a.y = y;
   a.w = w;
@@ -823,7 +838,8 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
   const bool mixed = p.prec == GLM_MIXED;
   pass_stats(p, &f->stats);
   GLM_CHECK(launch_alpha(f->d_inst(), p.B, Om, f->at<double>(p.o_alpha),
-                         mixed ? f->at<float>(p.o_Om32) : nullptr, s));
+                         mixed ? f->at<float>(p.o_Om32) : nullptr,
+                         p.deq ? f->at<double>(p.o_deq) : nullptr, s));
   GLM_CHECK(launch_state_init(f->d_inst(), p.B, f->at<int>(p.o_flags), p.nblk,
                               f->at<int>(p.o_rinst_index), f->d_st(), f->d_active(),
                               f->at<int>(p.o_ost), s));
@@ -863,6 +879,7 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
       {
         PassLaunch<double> a = pass_args<double>(f, f->X, Om, y, u_out, y64, nullptr, false);
         a.alpha = f->at<double>(p.o_mone);
+        a.deq = nullptr;
         a.w_nonzero = step > 0;
         if (int rc = run_pass_b<double>(f, a, PASS_B_INIT, s)) return rc;
       }
@@ -997,9 +1014,13 @@ hipError_t timed_apply(glm_factor* f, int p, const double* W, const double* T, d
 // panel (each panel's block reflector applied to the columns right of it),
 // take the reduced regressors from R and factor the reduced problem in the
 // rest of the workspace.
+int factor_entry(const glm_shape* shape, glm_precision prec, const double* X,
+                 const double* Rc, void* ws, size_t ws_bytes, hipStream_t stream,
+                 glm_factor** out, bool pinned);
+
 int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
                    const double* Rc, void* ws, size_t ws_bytes, hipStream_t stream,
-                   glm_factor** out) {
+                   glm_factor** out, bool pinned) {
   glm_factor* f = new (std::nothrow) glm_factor();
   if (!f) return GLM_EINVAL;
   int rc = make_red_plan(shape, base, f->rp);
@@ -1037,8 +1058,8 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
     delete f;
     return GLM_EHIP;
   }
-  rc = glm_qr_factor(&f->rp.sub, base, f->at<double>(r.o_Xr), Rc, f->ws + r.o_sub,
-                     r.sub_bytes, stream, &f->sub);
+  rc = factor_entry(&f->rp.sub, base, f->at<double>(r.o_Xr), Rc, f->ws + r.o_sub,
+                    r.sub_bytes, stream, &f->sub, pinned);
   if (rc != GLM_OK) {
     delete f;
     return rc;
@@ -1081,14 +1102,13 @@ extern "C" {
 int glm_validate_shape(const glm_shape* shape) { return validate(shape); }
 
 size_t glm_workspace_bytes(const glm_shape* shape, glm_precision prec) {
+  if (!prec_ok(prec)) return 0;
   if ((int)prec & GLM_REDUCED) {
     const glm_precision base = (glm_precision)((int)prec & ~GLM_REDUCED);
-    if (base != GLM_FP64 && base != GLM_MIXED) return 0;
     RedPlan r;
     if (make_red_plan(shape, base, r) != GLM_OK) return 0;
     return r.total;
   }
-  if (prec != GLM_FP64 && prec != GLM_MIXED) return 0;
   Plan p;
   if (make_plan(shape, prec, p) != GLM_OK) return 0;
   return p.total;
@@ -1097,14 +1117,23 @@ size_t glm_workspace_bytes(const glm_shape* shape, glm_precision prec) {
 int glm_qr_factor(const glm_shape* shape, glm_precision prec, const double* X,
                   const double* Rc, void* ws, size_t ws_bytes, hipStream_t stream,
                   glm_factor** out) {
+  return factor_entry(shape, prec, X, Rc, ws, ws_bytes, stream, out, true);
+}
+
+}  // extern "C"
+
+namespace {
+
+int factor_entry(const glm_shape* shape, glm_precision prec, const double* X,
+                 const double* Rc, void* ws, size_t ws_bytes, hipStream_t stream,
+                 glm_factor** out, bool pinned) {
   if (!out || !X) return GLM_EINVAL;
   *out = nullptr;
+  if (!prec_ok(prec)) return GLM_EINVAL;
   if ((int)prec & GLM_REDUCED) {
     const glm_precision base = (glm_precision)((int)prec & ~GLM_REDUCED);
-    if (base != GLM_FP64 && base != GLM_MIXED) return GLM_EINVAL;
-    return factor_reduced(shape, base, X, Rc, ws, ws_bytes, stream, out);
+    return factor_reduced(shape, base, X, Rc, ws, ws_bytes, stream, out, pinned);
   }
-  if (prec != GLM_FP64 && prec != GLM_MIXED) return GLM_EINVAL;
   glm_factor* f = new (std::nothrow) glm_factor();
   if (!f) return GLM_EINVAL;
   int rc = make_plan(shape, prec, f->p);
@@ -1124,9 +1153,14 @@ int glm_qr_factor(const glm_shape* shape, glm_precision prec, const double* X,
   f->ws = static_cast<char*>(ws);
   f->X = X;
   f->Rc = Rc;
-  if (hipHostMalloc((void**)&f->h_count, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
-    delete f;
-    return GLM_EHIP;
+  if (pinned) {
+    if (hipHostMalloc((void**)&f->h_count, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+      delete f;
+      return GLM_EHIP;
+    }
+    f->h_count_pinned = true;
+  } else {
+    f->h_count = f->h_count_host;   // pageable: the poll copy completes at the stream sync
   }
   auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0) return hipSuccess;
@@ -1157,16 +1191,20 @@ int glm_qr_factor(const glm_shape* shape, glm_precision prec, const double* X,
       e = launch_qr(f->at<QRJob>(p.o_qrn), (int)p.qr_nb.size(), p.maxkc,
                     f->at<double>(p.o_Nb), f->at<double>(p.o_R), f->at<int>(p.o_flags), stream);
   }
-  if (!e && prec == GLM_MIXED)
+  if (!e && p.prec == GLM_MIXED)
     e = launch_to_float(f->at<double>(p.o_Q64), f->at<float>(p.o_Q32), p.sumMn, stream);
   if (e != hipSuccess) {
-    (void)hipHostFree(f->h_count);
+    if (f->h_count_pinned) (void)hipHostFree(f->h_count);
     delete f;
     return GLM_EHIP;
   }
   *out = f;
   return GLM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int glm_gls_solve(glm_factor* f, const double* Omega, const double* y, const double* r,
                   double tol, int32_t max_iter, double* beta, double* u, double* uc,
@@ -1216,8 +1254,8 @@ int glm_copy_factors(const glm_factor* f, double* Q, double* R, int32_t* rank,
 int glm_plan_passes(const glm_shape* shape, glm_precision prec, glm_stats* out) {
   if (!out) return GLM_EINVAL;
   *out = glm_stats{};
+  if (!prec_ok(prec)) return GLM_EINVAL;
   const glm_precision base = (glm_precision)((int)prec & ~GLM_REDUCED);
-  if (base != GLM_FP64 && base != GLM_MIXED) return GLM_EINVAL;
   Plan p;
   if ((int)prec & GLM_REDUCED) {
     RedPlan r;
@@ -1302,7 +1340,7 @@ void glm_factor_destroy(glm_factor* f) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
   }
-  if (f->h_count) (void)hipHostFree(f->h_count);
+  if (f->h_count_pinned) (void)hipHostFree(f->h_count);
   delete f;
 }
 

@@ -29,19 +29,26 @@ __global__ void k_fill(T* __restrict__ p, int64_t count, T v) {
     p[e] = v;
 }
 
-// alpha_b = max_i omega_ii (D = alpha I) and, when requested, a single-precision Omega.
+// alpha_b = max_i omega_ii (D = alpha I); when requested, the per-equation
+// scalars d_i = omega_ii of D = diag(d) (x) I_M (alpha for an equation with
+// omega_ii = 0 and for every equation of a restricted instance, which keeps
+// D = alpha I), and a single-precision Omega.
 __global__ void k_alpha(const InstDesc* __restrict__ insts, int B,
                         const double* __restrict__ Om, double* __restrict__ alpha,
-                        float* __restrict__ Om32) {
+                        float* __restrict__ Om32, double* __restrict__ deq) {
   const int b = blockIdx.x;
   if (b >= B) return;
   const InstDesc in = insts[b];
   const double* o = Om + in.om_off;
-  if (threadIdx.x == 0) {
-    double a = 0.0;
-    for (int i = 0; i < in.G; ++i) a = fmax(a, o[i * in.G + i]);
-    alpha[b] = (a > 0.0) ? a : 1.0;
-  }
+  double a = 0.0;
+  for (int i = 0; i < in.G; ++i) a = fmax(a, o[i * in.G + i]);
+  a = (a > 0.0) ? a : 1.0;
+  if (threadIdx.x == 0) alpha[b] = a;
+  if (deq)
+    for (int i = threadIdx.x; i < in.G; i += blockDim.x) {
+      const double di = o[i * in.G + i];
+      deq[in.blk0 + i] = (in.kc == 0 && di > 1e-300 * a) ? di : a;
+    }
   if (Om32)
     for (int e = threadIdx.x; e < in.G * in.G; e += blockDim.x) Om32[in.om_off + e] = (float)o[e];
 }
@@ -344,8 +351,8 @@ template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
 template hipError_t launch_fill<int>(int*, int64_t, int, hipStream_t);
 
 hipError_t launch_alpha(const InstDesc* insts, int B, const double* Om, double* alpha,
-                        float* Om32, hipStream_t s) {
-  hipLaunchKernelGGL(k_alpha, dim3(B), dim3(256), 0, s, insts, B, Om, alpha, Om32);
+                        float* Om32, double* deq, hipStream_t s) {
+  hipLaunchKernelGGL(k_alpha, dim3(B), dim3(256), 0, s, insts, B, Om, alpha, Om32, deq);
   return hipGetLastError();
 }
 

@@ -121,6 +121,7 @@ struct PassLaunch {
   const T* Q;
   const T* Om;
   const double* alpha;
+  const double* deq;   // per-block D scalars (D = diag(d) (x) I_M), or null: D = alpha I
   const RhsState* st;
   const T* y;
   T* w;
@@ -190,7 +191,7 @@ hipError_t launch_trisolve(const InstDesc* insts, const BlockDesc* blks, int nbl
 template <typename T>
 hipError_t launch_fill(T* p, int64_t count, T v, hipStream_t s);
 hipError_t launch_alpha(const InstDesc* insts, int B, const double* Om, double* alpha,
-                        float* Om32, hipStream_t s);
+                        float* Om32, double* deq, hipStream_t s);
 hipError_t launch_state_init(const InstDesc* insts, int B, const int* rankflag,
                              int rank_extra_base, const int* rinst_index, RhsState* st,
                              int* inst_active, int* ost, hipStream_t s);

@@ -39,6 +39,7 @@ struct VecArgs {
   const T* __restrict__ Q;        // Q (or X) of the precision of the pass
   const T* __restrict__ Om;       // Omega of the precision of the pass
   const double* __restrict__ alpha;
+  const double* __restrict__ deq;  // per-block D scalars, or null (D = alpha I)
   const RhsState* __restrict__ st;
   const T* __restrict__ y;        // right-hand side (A_RHS, B_INIT)
   T* w;
@@ -323,19 +324,28 @@ k_pass_b(VecArgs<T> a) {
       }
       const int64_t e0 = base + ((int64_t)t * G + i) * K;
       const int l0 = (t * G + i) * K;
+      // D = diag(d) (x) I_M: Pi_i = P_i / d_i, and c = sum_i d_i ||g_i||^2 is
+      // accumulated as alpha * sum_i (d_i / alpha) ||g_i||^2
+      T ia = ialpha;
+      double wgt = 1.0;
+      if (a.deq) {
+        const double di = a.deq[in.blk0 + i];
+        ia = (T)(1.0 / di);
+        wgt = di * s_ialpha;
+      }
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
         if (k < K && s_act[k]) {
           if (MODE == B_ITER) {
             const T lam = (T)s_lam[k];
-            const T gg = a.g[e0 + k] - lam * ialpha * (Bs[l0 + k] - qt[k]);
+            const T gg = a.g[e0 + k] - lam * ia * (Bs[l0 + k] - qt[k]);
             a.g[e0 + k] = gg;
             a.w[e0 + k] = a.w[e0 + k] - lam * Us[l0 + k];
-            cacc[k] += (double)gg * (double)gg;
+            cacc[k] += wgt * (double)gg * (double)gg;
           } else if (MODE == B_INIT) {
-            const T gg = -(Bs[l0 + k] - qt[k]) * ialpha;
+            const T gg = -(Bs[l0 + k] - qt[k]) * ia;
             a.g[e0 + k] = gg;
-            cacc[k] += (double)gg * (double)gg;
+            cacc[k] += wgt * (double)gg * (double)gg;
           } else {
             a.w[e0 + k] = qt[k];
           }
@@ -624,6 +634,7 @@ static VecArgs<T> to_args(const PassLaunch<T>& p) {
   a.Q = p.Q;
   a.Om = p.Om;
   a.alpha = p.alpha;
+  a.deq = p.deq;
   a.st = p.st;
   a.y = p.y;
   a.w = p.w;

@@ -96,6 +96,7 @@ struct Args3 {
   const T* __restrict__ Q;
   const T* __restrict__ Om;
   const double* __restrict__ alpha;
+  const double* __restrict__ deq;  // per-block D scalars, or null (D = alpha I)
   const RhsState* __restrict__ st;
   const T* __restrict__ y;
   T* w;
@@ -645,7 +646,15 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
   bool act = false;
 #pragma unroll
   for (int v = 0; v < KV; ++v) act = act || actk[v];
-  const T ialpha = (T)s_ialpha;
+  // D = diag(d) (x) I_M: this lane's equation scales g by 1 / d_i, and
+  // c = sum_i d_i ||g_i||^2 is accumulated as alpha * sum_i (d_i / alpha) ||g_i||^2
+  T ialpha = (T)s_ialpha;
+  double wgt = 1.0;
+  if (a.deq && on) {
+    const double di = a.deq[in.blk0 + i];
+    ialpha = (T)(1.0 / di);
+    wgt = di * s_ialpha;
+  }
   int kact = 0;
   for (int kk = 0; kk < K; ++kk) kact += s_act[kk];
   double cacc[KV];
@@ -725,7 +734,7 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
             if (actk[v]) {
               gn.v[v] = gv.v[v] - lam[v] * ialpha * (b[v] - qt[v]);
               wn.v[v] = wv.v[v] - lam[v] * uv.v[v];
-              cacc[v] += (double)gn.v[v] * (double)gn.v[v];
+              cacc[v] += wgt * (double)gn.v[v] * (double)gn.v[v];
             } else {
               gn.v[v] = gv.v[v];
               wn.v[v] = wv.v[v];
@@ -746,7 +755,7 @@ __global__ void __launch_bounds__(PNT) k_proj_b(Args3<T> a) {
           for (int v = 0; v < KV; ++v) {
             const T gg = -((yv.v[v] - b[v]) - qt[v]) * ialpha;
             gn.v[v] = gg;
-            if (actk[v]) cacc[v] += (double)gg * (double)gg;
+            if (actk[v]) cacc[v] += wgt * (double)gg * (double)gg;
           }
           // inactive right-hand sides keep their g (never read before INIT)
           gstore<T, KV>(a.g + e, gn);
@@ -786,6 +795,7 @@ Args3<T> to_args3(const PassLaunch<T>& p) {
   a.Q = p.Q;
   a.Om = p.Om;
   a.alpha = p.alpha;
+  a.deq = p.deq;
   a.st = p.st;
   a.y = p.y;
   a.w = p.w;

@@ -111,14 +111,19 @@ class SURSolver:
     """Owns one workspace and one factor handle for a fixed batch shape."""
 
     def __init__(self, layout: BatchLayout, precision: str = "fp64", device="cuda:0",
-                 reduce: bool = False):
+                 reduce: bool = False, precond: str = "scalar"):
         """reduce: solve through the SUR model reduction (one QR of
         W = [X_1 ... X_G] per instance; the iteration runs on min(M, n + 1)
         rotated observations).  Forward solves only: backward() and factors()
-        raise on such a solver."""
+        raise on such a solver.
+        precond: "scalar" (D = alpha I, alpha = max_i omega_ii) or "equation"
+        (D = diag(omega_ii) (x) I_M, one scalar per equation)."""
+        if precond not in ("scalar", "equation"):
+            raise ValueError(precond)
         self.layout = layout
         self.reduce = bool(reduce)
-        self.precision = _lib.PRECISIONS[precision] | (_lib.GLM_REDUCED if reduce else 0)
+        self.precision = (_lib.PRECISIONS[precision] | (_lib.GLM_REDUCED if reduce else 0)
+                          | (_lib.GLM_PRECOND_EQ if precond == "equation" else 0))
         self.device = torch.device(device)
         self._shape = layout.shape()
         rc = _lib.glm_validate_shape(self._shape)

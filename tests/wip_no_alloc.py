@@ -1,0 +1,87 @@
+"""glm_qr_factor_static (the factorization on the library's static device
+scratch, for callers that cannot allocate device memory) against
+glm_qr_factor with a caller workspace: two calls in a row on one GPU, the
+second with a smaller batch, each followed by glm_gls_solve; beta and u
+must agree to 1e-10 per (instance, rhs), normwise and element-wise, and
+both must match the oracle.  A shape whose workspace exceeds the scratch
+is refused before any work is enqueued."""
+import numpy as np
+import pytest
+
+import synth
+from conftest import rel_err
+from oracle import gls
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def glmlib():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2510_14471_amd as glm
+    return glm
+
+
+def _solve(glm, handle, lay, d, tol):
+    f64 = torch.float64
+    beta = torch.empty(lay.off_b[-1], dtype=f64, device="cuda")
+    u = torch.empty(lay.off_y[-1], dtype=f64, device="cuda")
+    info = torch.empty(lay.n_rhs, dtype=torch.int32, device="cuda")
+    glm._lib.glm_gls_solve(handle, d["Omega"], d["y"], None, tol, 0, beta, u, None, info,
+                           None)
+    torch.cuda.synchronize()
+    return (glm.unpack(lay, beta, "beta"), glm.unpack(lay, u, "u"),
+            glm.unpack(lay, info, "rhs"))
+
+
+def _compare(insts, a, b):
+    for bi, inst in enumerate(insts):
+        beta_o, U_o = gls.sur_gls(inst)
+        for k in range(inst.K):
+            for x, y, o in ((a[0][bi][:, k], b[0][bi][:, k], beta_o[:, k]),
+                            (a[1][bi][:, :, k], b[1][bi][:, :, k], U_o[:, :, k])):
+                assert rel_err(x, y) <= TOL and rel_err(x, o) <= TOL, (bi, k)
+                assert np.abs(x - y).max() <= TOL * np.abs(y).max(), (bi, k)
+            assert a[2][bi][k] in (0, 1) and b[2][bi][k] in (0, 1)
+
+
+@pytest.mark.parametrize("precision,reduce", [("mixed", False), ("fp64", True)])
+def test_static_scratch_factor_matches_workspace_factor(glmlib, precision, reduce):
+    lib = glmlib._lib
+    prec = lib.PRECISIONS[precision] | (lib.GLM_REDUCED if reduce else 0)
+    tol = 1e-13 if precision == "mixed" else 1e-12
+    batches = [list(synth.small_batch(seed=301, B=6, G_rng=(2, 7), M_rng=(100, 600),
+                                      n_rng=(2, 9), K_rng=(1, 6))),
+               list(synth.small_batch(seed=303, B=3, G_rng=(2, 4), M_rng=(40, 150),
+                                      n_rng=(1, 5), K_rng=(1, 3)))]
+    for call, insts in enumerate(batches):
+        lay, d = glmlib.pack_instances(insts)
+        shape = lay.shape()
+        print(f"[case] static scratch call {call} {precision} reduce={reduce} "
+              f"B={len(insts)} ws={lib.glm_workspace_bytes(shape, prec)}", flush=True)
+        assert 0 < lib.glm_workspace_bytes(shape, prec) <= 64 << 20
+        # reference: the caller-workspace entry point
+        ws = torch.empty(lib.glm_workspace_bytes(shape, prec), dtype=torch.uint8,
+                         device="cuda")
+        h_ref = lib.glm_qr_factor(shape, prec, d["X"], None, ws)
+        ref = _solve(glmlib, h_ref, lay, d, tol)
+        lib.glm_factor_destroy(h_ref)
+        # the static-scratch entry point
+        h = lib.glm_qr_factor_static(shape, prec, d["X"], None)
+        got = _solve(glmlib, h, lay, d, tol)
+        lib.glm_factor_destroy(h)
+        _compare(insts, got, ref)
+
+
+def test_static_scratch_refuses_oversized_shapes(glmlib):
+    lib = glmlib._lib
+    shape = lib.Shape([32], [200_000], [16], [20] * 32)
+    assert lib.glm_workspace_bytes(shape, lib.GLM_FP64) > 64 << 20
+    X = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.GLMError, match="workspace"):
+        lib.glm_qr_factor_static(shape, lib.GLM_FP64, X, None)
