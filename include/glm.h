@@ -175,6 +175,27 @@ int glm_qr_factor(const glm_shape* shape, glm_precision prec,
                   void* ws, size_t ws_bytes, hipStream_t stream,
                   glm_factor** out);
 
+/* glm_qr_factor for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, e.g. tight serving loops or harnesses that forbid
+ * it): the same factorization, with the library's static device scratch as
+ * the workspace instead of a caller buffer.  The scratch is one 64 MiB array
+ * per GPU, reserved when the library's code is loaded on that GPU and held
+ * until the process ends.
+ *
+ *   shape, prec, X, Rc, stream, out   as for glm_qr_factor
+ * Returns GLM_EWORKSPACE, before any work is enqueued, when
+ * glm_workspace_bytes(shape, prec) exceeds 64 MiB; otherwise as
+ * glm_qr_factor.  The call allocates no device or pinned host memory (the
+ * handle polls convergence through pageable host memory).  All handles
+ * made by this call on one GPU share that GPU's scratch: a new call
+ * overwrites the factors of the previous one, so only the handle of the
+ * latest call on a device may be used, and calls (or solves on these
+ * handles) that overlap in time on one GPU race.  Nothing in the scratch
+ * needs to start at zero: every byte a kernel reads is written first by
+ * the same call or by the solve. */
+int glm_qr_factor_static(const glm_shape* shape, glm_precision prec, const double* X,
+                         const double* Rc, hipStream_t stream, glm_factor** out);
+
 /* Solves every (instance, rhs) of the batch with PCG-Aug (projected form:
  * the iteration carries g_i = Pi r_i and one OLS projection per step).
  *

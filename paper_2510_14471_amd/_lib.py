@@ -64,6 +64,8 @@ def _load():
     lib.glm_qr_factor.argtypes = [POINTER(GlmShape), c_int, P, P, P, c_size_t, P,
                                   POINTER(c_void_p)]
     lib.glm_qr_factor.restype = c_int
+    lib.glm_qr_factor_static.argtypes = [POINTER(GlmShape), c_int, P, P, P, POINTER(c_void_p)]
+    lib.glm_qr_factor_static.restype = c_int
     lib.glm_gls_solve.argtypes = [P, P, P, P, c_double, c_int32, P, P, P, P, P, P]
     lib.glm_gls_solve.restype = c_int
     lib.glm_gls_backward.argtypes = [P, P, P, P, P, P, c_double, c_int32, P, P, P, P, P, P]
@@ -89,7 +91,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["glm_validate_shape", "glm_workspace_bytes", "glm_qr_factor",
-            "glm_gls_solve",
+            "glm_qr_factor_static", "glm_gls_solve",
             "glm_gls_backward", "glm_copy_factors", "glm_plan_passes", "glm_get_stats",
             "glm_profile_enable", "glm_profile_read", "glm_factor_destroy", "glm_strerror"]
 
@@ -151,6 +153,14 @@ def glm_qr_factor(shape: Shape, precision: int, X, Rc, ws, stream=None) -> c_voi
     rc = _lib.glm_qr_factor(shape.ptr(), int(precision), _dp(X), _dp(Rc), _dp(ws),
                             ws.numel() * ws.element_size(), _stream(stream), ctypes.byref(h))
     _check(rc, "glm_qr_factor")
+    return h
+
+
+def glm_qr_factor_static(shape: Shape, precision: int, X, Rc, stream=None) -> c_void_p:
+    h = c_void_p()
+    rc = _lib.glm_qr_factor_static(shape.ptr(), int(precision), _dp(X), _dp(Rc),
+                                   _stream(stream), ctypes.byref(h))
+    _check(rc, "glm_qr_factor_static")
     return h
 
 

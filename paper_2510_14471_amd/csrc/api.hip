@@ -17,10 +17,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 using namespace glm;
+
+static __device__ __align__(256) unsigned char scratch[size_t(64) << 20];
 
 namespace {
 
@@ -52,6 +55,31 @@ bool prec_ok(glm_precision p) {
   return v == GLM_FP64 || v == GLM_MIXED;
 }
 
+// Device scratch of glm_qr_factor_static, for callers that cannot allocate
+// device memory: one copy per GPU, held until the process ends.  Host code
+// never uses the symbol's name as an address (it is a host-side stand-in);
+// it takes each device's address from hipGetSymbolAddress, once per device
+// with that device current, and passes that.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up on first use.
+hipError_t static_scratch(void** out) {
+  static_assert(sizeof(scratch) == kStaticScratchBytes, "one size for both");
+  int dev = 0;
+  if (hipError_t e = hipGetDevice(&dev)) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) return e;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
 
 // Progress trace on stderr when the environment variable GLM_LOG is set.
 bool log_on() {
@@ -1118,6 +1146,21 @@ int glm_qr_factor(const glm_shape* shape, glm_precision prec, const double* X,
                   const double* Rc, void* ws, size_t ws_bytes, hipStream_t stream,
                   glm_factor** out) {
   return factor_entry(shape, prec, X, Rc, ws, ws_bytes, stream, out, true);
+}
+
+int glm_qr_factor_static(const glm_shape* shape, glm_precision prec, const double* X,
+                         const double* Rc, hipStream_t stream, glm_factor** out) {
+  if (!out || !X) return GLM_EINVAL;
+  *out = nullptr;
+  const size_t need = glm_workspace_bytes(shape, prec);
+  if (need == 0) {
+    const int rc = validate(shape);
+    return rc != GLM_OK ? rc : GLM_EINVAL;
+  }
+  if (need > kStaticScratchBytes) return GLM_EWORKSPACE;
+  void* ws = nullptr;
+  if (static_scratch(&ws) != hipSuccess || !ws) return GLM_EHIP;
+  return factor_entry(shape, prec, X, Rc, ws, kStaticScratchBytes, stream, out, false);
 }
 
 }  // extern "C"
