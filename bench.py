@@ -33,10 +33,8 @@ KERNEL_SOURCES = ["paper_2510_14471_amd/csrc/proj.hip", "paper_2510_14471_amd/cs
                   "paper_2510_14471_amd/csrc/qr_panel.h"]
 PASS_NAMES = {0: "k_proj_a<float> (pass A: u <- g + mu u, B = U Omega, d = u.B, T += Q^T B)",
               1: "k_proj_b<float> (pass B: g -= (lambda/alpha)(B - Q T), w -= lambda u, c = g.g)",
-              2: "k_red_apply_z<false> + k_red_apply_c<false> (model reduction: C <- (I - V T' V^T) C, "
-                 "block reflector of a 32-column Householder panel of W = [X_1 ... X_G], on Y (Q^T Y) "
-                 "and U (Q Z) in the solve; partial V^T C per 512-row segment, then the update; "
-                 "one launch = the pair)"}
+              2: "k_red_gemm_tn (model reduction: reduced responses Y_red = Q1^T Y, "
+                 "Q1 = first n + 1 columns of the Q of W = [X_1 ... X_G])"}
 
 
 def log(msg):

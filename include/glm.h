@@ -86,15 +86,16 @@ typedef enum glm_precision {
                      (the remark on reducing the SUR model in the SUR section).
                      One Householder QR of W = [X_1 ... X_G] = Q [R; 0] per
                      instance (double precision) rotates every equation by Q^T;
-                     the solve then runs PCG-Aug on the first min(M, n + 1)
+                     the solve then runs PCG-Aug on the first Mr = min(M, n + 1)
                      rotated observations, which give the GLS estimate of the
-                     full model, and returns beta and u of the full model
-                     (u = Q [u_reduced; (Q^T Y)_{rest} Omega^-1]).  Requires a
-                     positive definite Omega (otherwise the instance's rhs
-                     report GLM_INFO_BREAKDOWN) and G_b <= 64 (otherwise
-                     GLM_EUNSUPPORTED).  glm_gls_backward and
-                     glm_copy_factors return GLM_EUNSUPPORTED on such a
-                     handle.                                                     */
+                     full model, and returns beta and u of the full model,
+                     u = Q [u_reduced; (Q^T Y)_{rest} Omega^g] with Omega^g a
+                     generalized inverse of Omega (the inverse when Omega is
+                     positive definite; for a singular Omega u is, as on the
+                     unreduced path, one of the solutions, Sigma u unique).
+                     The factorization keeps Q1 = Q [I; 0] (M x Mr) explicit.
+                     glm_gls_backward runs the adjoint through the same
+                     reduction; glm_copy_factors returns GLM_EUNSUPPORTED.     */
   GLM_PRECOND_EQ = 8 /* flag, OR-ed into the precision for glm_workspace_bytes,
                      glm_qr_factor(_static) and glm_plan_passes: the
                      preconditioner's auxiliary matrix is one scalar per
@@ -231,7 +232,10 @@ int glm_gls_solve(glm_factor* f, const double* Omega, const double* y,
  *             dL = <dOmega, E> for every symmetric perturbation E)
  *   dX_i    = -sum_k ( l_u,i beta_i^T + u_i l_beta,i^T )
  * Defined for nonsingular Omega.  Restricted instances are solved in the
- * restricted geometry (gradients w.r.t. R_c and r are not produced).
+ * restricted geometry (gradients w.r.t. R_c and r are not produced).  On a
+ * GLM_REDUCED handle the adjoint system goes through the same reduction
+ * (Q1^T g_u, the reduced adjoint with lower right-hand side g_beta, then
+ * l_u of the full model) and the gradients are those of the full model.
  *
  *   beta, u   device, the forward outputs
  *   g_beta    device, n_b x K_b per instance (dL/dbeta)
@@ -277,8 +281,8 @@ int glm_get_stats(const glm_factor* f, glm_stats* out);
  * the number of launches, their summed duration in milliseconds and the
  * summed algorithmic bytes; it then clears the counters.  On a GLM_REDUCED
  * handle ids 0 and 1 report the passes of the reduced solve and id 2 the
- * block-reflector applications of glm_gls_solve (Q^T Y and Q Z; the target
- * rows read and written once plus the panel's reflectors read once); the
+ * reduced responses Q1^T Y of glm_gls_solve (and of the adjoint in
+ * glm_gls_backward; Q1 and Y read once, the Mr rows written once); the
  * factorization runs before its handle exists and is not timed.  Id 2 reads
  * zero on other handles. */
 int glm_profile_enable(glm_factor* f, int on);

@@ -471,20 +471,54 @@ namespace {
 // equations and blocks with min(M, n + 1) observations) and the layout of
 // the reduction buffers, followed by the reduced problem's own workspace.
 struct RedPlan {
-  int B = 0, maxpan = 0, maxn = 0, maxGK = 0, maxM = 0;
+  int B = 0, maxpan = 0, maxn = 0, maxM = 0, maxMr = 0;
+  int uchunks = 0, dchunks = 0;   // row chunks of k_red_u and k_red_delta
   std::vector<RedDesc> d;
   // the device copy of the descriptors, tallest instance first: every
   // reduction kernel takes its instance from its descriptor, so the order
   // only sets the launch order, and the sequential panel kernel then
   // schedules the longest jobs first
   std::vector<RedDesc> d_dev;
+  // output tiles of Q1^T Y (t1) and of Q1 D (t2), grouped by XCD
+  std::vector<GemmTile> t1, t2;
   std::vector<int32_t> G, M, K, k, n;
   glm_shape sub{};
   int64_t sumMn = 0, sumMGK = 0, sumMrn = 0, sumMrGK = 0, sumn = 0, sumT = 0, sumG2 = 0,
-          sumZp = 0;
-  size_t o_desc = 0, o_W = 0, o_tau = 0, o_T = 0, o_Yt = 0, o_Xr = 0, o_yr = 0, o_ur = 0,
-         o_Oinv = 0, o_Zp = 0, o_sub = 0, sub_bytes = 0, total = 0;
+          sumZp = 0, sumMMr = 0, sumnK = 0;
+  double gemm1_bytes = 0.0;   // algorithmic bytes of one Q1^T Y over the batch
+  size_t o_desc = 0, o_W = 0, o_tau = 0, o_T = 0, o_Q1 = 0, o_Xr = 0, o_yr = 0, o_ur = 0,
+         o_dd = 0, o_Og = 0, o_Ow = 0, o_sing = 0, o_t1 = 0, o_t2 = 0, o_Zp = 0, o_lb = 0,
+         o_sub = 0, sub_bytes = 0, total = 0;
 };
+
+// Tile table of a batched product: every instance's output tiles (rows x
+// cols in 64 x 64 tiles) go to one XCD, chosen greedily by the work already
+// there (weight per tile `w`, instances in device order), and workgroup x of
+// the launch runs on XCD x mod 8: an instance's tiles share one L2.
+std::vector<GemmTile> xcd_tiles(const std::vector<RedDesc>& dd, bool out_rows_full) {
+  constexpr int kXcd = 8;
+  std::vector<std::vector<GemmTile>> lists(kXcd);
+  double load[kXcd] = {0};
+  for (int q = 0; q < (int)dd.size(); ++q) {
+    const RedDesc& d = dd[q];
+    const int rows = out_rows_full ? d.M : d.Mr, cols = d.G * d.K;
+    const double w = out_rows_full ? (double)d.Mr : (double)d.M;   // reduction length
+    int x = 0;
+    for (int c = 1; c < kXcd; ++c)
+      if (load[c] < load[x]) x = c;
+    for (int i0 = 0; i0 < rows; i0 += 64)
+      for (int j0 = 0; j0 < cols; j0 += 64) {
+        lists[x].push_back(GemmTile{q, i0, j0, 0});
+        load[x] += w;
+      }
+  }
+  size_t lmax = 0;
+  for (const auto& l : lists) lmax = std::max(lmax, l.size());
+  std::vector<GemmTile> out(lmax * kXcd, GemmTile{-1, 0, 0, 0});
+  for (int x = 0; x < kXcd; ++x)
+    for (size_t q = 0; q < lists[x].size(); ++q) out[q * kXcd + x] = lists[x][q];
+  return out;
+}
 
 int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
   int rc = validate(s);
@@ -493,12 +527,11 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
   r.B = s->batch;
   int64_t noff = 0, rhs = 0, om = 0;
   for (int b = 0; b < r.B; ++b) {
-    // the Omega^-1 of the dropped rows is formed in LDS for G <= 64
-    if (s->G[b] > 64) return GLM_EUNSUPPORTED;
     RedDesc d{};
     d.M = s->M[b];
     d.G = s->G[b];
     d.K = s->K[b];
+    d.inst = b;
     int n = 0;
     for (int i = 0; i < d.G; ++i) n += s->n[noff + i];
     d.n = n;
@@ -506,6 +539,8 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     d.kr = std::min(d.M, n);
     d.rhs0 = (int)rhs;
     d.w_off = r.sumMn;
+    d.q1_off = r.sumMMr;
+    d.b_off = r.sumnK;
     d.v_off = r.sumMGK;
     d.xr_off = r.sumMrn;
     d.vr_off = r.sumMrGK;
@@ -514,18 +549,25 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     d.om_off = om;
     d.zp_off = r.sumZp;
     const int npan = (d.kr + RED_PANEL - 1) / RED_PANEL;
+    const int P = d.G * d.K;
+    const int rows = std::max(1, std::min(32, 4096 / P));
+    r.uchunks = std::max(r.uchunks, (d.M + rows - 1) / rows);
+    r.dchunks = std::max(r.dchunks, (d.Mr + rows - 1) / rows);
     r.maxpan = std::max(r.maxpan, npan);
     r.maxn = std::max(r.maxn, n);
-    r.maxGK = std::max(r.maxGK, d.G * d.K);
     r.maxM = std::max(r.maxM, d.M);
+    r.maxMr = std::max(r.maxMr, d.Mr);
     r.sumMn += (int64_t)d.M * n;
-    r.sumMGK += (int64_t)d.M * d.G * d.K;
+    r.sumMMr += (int64_t)d.M * d.Mr;
+    r.sumnK += (int64_t)n * d.K;
+    r.sumMGK += (int64_t)d.M * P;
     r.sumMrn += (int64_t)d.Mr * n;
-    r.sumMrGK += (int64_t)d.Mr * d.G * d.K;
+    r.sumMrGK += (int64_t)d.Mr * P;
     r.sumn += n;
     r.sumT += (int64_t)npan * RED_PANEL * RED_PANEL;
-    r.sumZp += (int64_t)((d.M + RED_SEG - 1) / RED_SEG) * RED_PANEL *
-               std::max(n, d.G * d.K);
+    r.sumZp += (int64_t)((d.M + RED_SEG - 1) / RED_SEG) *
+               std::max<int64_t>((int64_t)RED_PANEL * (n + 1), (int64_t)d.G * d.G);
+    r.gemm1_bytes += 8.0 * ((double)d.M * d.Mr + (double)d.M * P + (double)d.Mr * P);
     om += (int64_t)d.G * d.G;
     r.sumG2 = om;
     rhs += d.K;
@@ -540,6 +582,8 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
   r.d_dev = r.d;
   std::stable_sort(r.d_dev.begin(), r.d_dev.end(),
                    [](const RedDesc& a, const RedDesc& b) { return a.M > b.M; });
+  r.t1 = xcd_tiles(r.d_dev, false);
+  r.t2 = xcd_tiles(r.d_dev, true);
   r.sub.batch = r.B;
   r.sub.G = r.G.data();
   r.sub.M = r.M.data();
@@ -559,15 +603,21 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     return at;
   };
   r.o_desc = take(sizeof(RedDesc) * r.d.size());
+  r.o_t1 = take(sizeof(GemmTile) * r.t1.size());
+  r.o_t2 = take(sizeof(GemmTile) * r.t2.size());
   r.o_W = take(8 * r.sumMn);
   r.o_tau = take(8 * r.sumn);
   r.o_T = take(8 * r.sumT);
-  r.o_Yt = take(8 * r.sumMGK);
+  r.o_Q1 = take(8 * r.sumMMr);
   r.o_Xr = take(8 * r.sumMrn);
   r.o_yr = take(8 * r.sumMrGK);
   r.o_ur = take(8 * r.sumMrGK);
-  r.o_Oinv = take(8 * r.sumG2);
+  r.o_dd = take(8 * r.sumMrGK);
+  r.o_Og = take(8 * r.sumG2);
+  r.o_Ow = take(8 * r.sumG2);
+  r.o_sing = take(4 * (size_t)r.B);
   r.o_Zp = take(8 * r.sumZp);
+  r.o_lb = take(8 * r.sumnK);
   r.o_sub = take(r.sub_bytes);
   r.total = o;
   return GLM_OK;
@@ -1005,43 +1055,30 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
 
 namespace {
 
-// One block-reflector apply over the batch; while profiling, bracketed by HIP
-// events (kernel id 2) with its algorithmic bytes counted on the host: the
-// target rows [c0, M) read and written once plus the panel's V read once.
-hipError_t timed_apply(glm_factor* f, int p, const double* W, const double* T, double* C,
-                       int target_w, int trans, int maxcols, hipStream_t s) {
+// Y_red = Q1^T Y over the batch; while profiling, bracketed by HIP events
+// (kernel id 2) with its algorithmic bytes counted on the host: Q1 and Y read
+// once, Y_red written once.
+int timed_gemm1(glm_factor* f, const double* Y, double* Yr, hipStream_t s) {
   const RedPlan& r = f->rp;
-  const RedDesc* dd = f->at<RedDesc>(r.o_desc);
   EventPair e{};
   if (f->prof) {
     e = get_event(f, 2);
-    if (hipError_t x = hipEventRecord(e.a, s)) return x;
-    const int c0 = p * RED_PANEL;
-    double by = 0.0;
-    for (const RedDesc& d : r.d) {
-      if (c0 >= d.kr) continue;
-      const int w = std::min(RED_PANEL, d.kr - c0);
-      const double rows = (double)(d.M - c0);
-      const double ncols = target_w ? (double)(d.n - c0 - w) : (double)d.G * d.K;
-      if (ncols <= 0) continue;
-      by += rows * (16.0 * ncols + 8.0 * w);
-    }
-    f->prof_bytes_host += by;
+    GLM_CHECK(hipEventRecord(e.a, s));
+    f->prof_bytes_host += r.gemm1_bytes;
   }
-  hipError_t x = launch_red_apply(dd, r.B, p, W, T, C, f->at<double>(r.o_Zp), target_w, trans,
-                                  maxcols, r.maxM - p * RED_PANEL, s);
-  if (x) return x;
+  GLM_CHECK(launch_red_gemm_tn(f->at<RedDesc>(r.o_desc), f->at<GemmTile>(r.o_t1),
+                               (int)r.t1.size(), f->at<double>(r.o_Q1), Y, Yr, s));
   if (f->prof) {
-    if (hipError_t y = hipEventRecord(e.b, s)) return y;
+    GLM_CHECK(hipEventRecord(e.b, s));
     f->ev_used.push_back(e);
   }
-  return hipSuccess;
+  return GLM_OK;
 }
 
 // glm_qr_factor with GLM_REDUCED: copy X, factor W = [X_1 ... X_G] panel by
 // panel (each panel's block reflector applied to the columns right of it),
-// take the reduced regressors from R and factor the reduced problem in the
-// rest of the workspace.
+// form Q1 = Q [I; 0] backwards, take the reduced regressors from R and
+// factor the reduced problem in the rest of the workspace.
 int factor_entry(const glm_shape* shape, glm_precision prec, const double* X,
                  const double* Rc, void* ws, size_t ws_bytes, hipStream_t stream,
                  glm_factor** out, bool pinned);
@@ -1074,14 +1111,29 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
   const RedDesc* dd = f->at<RedDesc>(r.o_desc);
   double* W = f->at<double>(r.o_W);
   double* T = f->at<double>(r.o_T);
-  hipError_t e = hipMemcpyAsync(f->ws + r.o_desc, r.d_dev.data(), sizeof(RedDesc) * r.d_dev.size(),
-                                hipMemcpyHostToDevice, stream);
+  double* Q1 = f->at<double>(r.o_Q1);
+  double* Zp = f->at<double>(r.o_Zp);
+  // the descriptor vectors live in the handle, so the copies may stay in flight
+  hipError_t e = hipMemcpyAsync(f->ws + r.o_desc, r.d_dev.data(),
+                                sizeof(RedDesc) * r.d_dev.size(), hipMemcpyHostToDevice, stream);
+  if (!e)
+    e = hipMemcpyAsync(f->ws + r.o_t1, r.t1.data(), sizeof(GemmTile) * r.t1.size(),
+                       hipMemcpyHostToDevice, stream);
+  if (!e)
+    e = hipMemcpyAsync(f->ws + r.o_t2, r.t2.data(), sizeof(GemmTile) * r.t2.size(),
+                       hipMemcpyHostToDevice, stream);
   if (!e) e = hipMemcpyAsync(W, X, 8 * r.sumMn, hipMemcpyDeviceToDevice, stream);
   for (int p = 0; p < r.maxpan && !e; ++p) {
     e = launch_red_panel(dd, r.B, p, W, f->at<double>(r.o_tau), T, stream);
-    if (!e) e = timed_apply(f, p, W, T, W, 1, 1, r.maxn - p * RED_PANEL, stream);
+    if (!e)
+      e = launch_red_apply(dd, r.B, p, W, T, W, Zp, 0, 1, r.maxn - p * RED_PANEL,
+                           r.maxM - p * RED_PANEL, stream);
   }
-  if (!e) e = launch_red_extract(dd, r.B, W, nullptr, f->at<double>(r.o_Xr), nullptr, stream);
+  if (!e) e = launch_red_qinit(dd, r.B, Q1, stream);
+  for (int p = r.maxpan - 1; p >= 0 && !e; --p)
+    e = launch_red_apply(dd, r.B, p, W, T, Q1, Zp, 1, 0, r.maxMr - p * RED_PANEL,
+                         r.maxM - p * RED_PANEL, stream);
+  if (!e) e = launch_red_extract(dd, r.B, W, f->at<double>(r.o_Xr), stream);
   if (e != hipSuccess) {
     delete f;
     return GLM_EHIP;
@@ -1096,30 +1148,72 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
   return GLM_OK;
 }
 
-// glm_gls_solve on a reduced handle: Y -> Q^T Y, the reduced solve on its
-// first Mr rows, then u = Q [u_reduced ; (Q^T Y)_{t >= Mr} Omega^-1].
+// The full model's u-like vector from the reduced solution:
+//   U = (Y - [X_i b_i]) Omega^g  (+ Q1 (U_red - U_red Omega Omega^g) where
+// Omega is singular).  Y may be null (zero).
+int red_full_u(glm_factor* f, const double* Omega, const double* Y, const double* b,
+               double* U, hipStream_t s) {
+  const RedPlan& rp = f->rp;
+  const RedDesc* dd = f->at<RedDesc>(rp.o_desc);
+  int* sing = f->at<int>(rp.o_sing);
+  GLM_CHECK(launch_red_ginv(dd, rp.B, Omega, f->at<double>(rp.o_Ow), f->at<double>(rp.o_Og),
+                            sing, s));
+  GLM_CHECK(launch_red_u(dd, rp.B, rp.uchunks, f->sub->d_inst(), f->sub->d_blk(), f->X, b, Y,
+                         f->at<double>(rp.o_Og), U, s));
+  std::vector<int> hs(rp.B, 0);
+  GLM_CHECK(hipMemcpyAsync(hs.data(), sing, 4 * (size_t)rp.B, hipMemcpyDeviceToHost, s));
+  GLM_CHECK(hipStreamSynchronize(s));
+  bool any = false;
+  for (int v : hs) any = any || v != 0;
+  if (any)
+    GLM_CHECK(launch_red_singular(dd, rp.B, rp.dchunks, f->at<GemmTile>(rp.o_t2),
+                                  (int)rp.t2.size(), sing, Omega, f->at<double>(rp.o_Og),
+                                  f->at<double>(rp.o_Q1), f->at<double>(rp.o_ur),
+                                  f->at<double>(rp.o_dd), U, s));
+  return GLM_OK;
+}
+
+// glm_gls_solve on a reduced handle: Y_red = Q1^T Y, the reduced solve on its
+// Mr rows, then the full model's u.
 int solve_reduced(glm_factor* f, const double* Omega, const double* y, const double* r,
                   double tol, int32_t max_iter, double* beta, double* u, double* uc,
                   int32_t* info, int32_t* iters, hipStream_t stream) {
   const RedPlan& rp = f->rp;
-  const RedDesc* dd = f->at<RedDesc>(rp.o_desc);
-  const double* W = f->at<double>(rp.o_W);
-  const double* T = f->at<double>(rp.o_T);
-  double* Yt = f->at<double>(rp.o_Yt);
-  double* ur = f->at<double>(rp.o_ur);
-  GLM_CHECK(hipMemcpyAsync(Yt, y, 8 * rp.sumMGK, hipMemcpyDeviceToDevice, stream));
-  for (int p = 0; p < rp.maxpan; ++p)
-    GLM_CHECK(timed_apply(f, p, W, T, Yt, 0, 1, rp.maxGK, stream));
-  GLM_CHECK(launch_red_extract(dd, rp.B, W, Yt, nullptr, f->at<double>(rp.o_yr), stream));
-  int rc = glm_gls_solve(f->sub, Omega, f->at<double>(rp.o_yr), r, tol, max_iter, beta, ur, uc,
-                         info, iters, stream);
+  if (int rc = timed_gemm1(f, y, f->at<double>(rp.o_yr), stream)) return rc;
+  int rc = glm_gls_solve(f->sub, Omega, f->at<double>(rp.o_yr), r, tol, max_iter, beta,
+                         f->at<double>(rp.o_ur), uc, info, iters, stream);
   if (rc != GLM_OK) return rc;
-  GLM_CHECK(launch_red_tail(dd, rp.B, rp.maxM, Omega, f->at<double>(rp.o_Oinv), Yt, ur, u, info,
-                            stream));
-  for (int p = rp.maxpan - 1; p >= 0; --p)
-    GLM_CHECK(timed_apply(f, p, W, T, u, 0, 0, rp.maxGK, stream));
+  if ((rc = red_full_u(f, Omega, y, beta, u, stream))) return rc;
   f->stats = f->sub->stats;
-  f->stats.launches += 2 * rp.maxpan + 2;
+  f->stats.launches += 4;
+  return GLM_OK;
+}
+
+// glm_gls_backward on a reduced handle: the adjoint system is the augmented
+// system with right-hand side [g_u; g_beta], so it goes through the same
+// reduction (lower right-hand side g_beta on the reduced problem); then the
+// gradients of the full model.
+int backward_reduced(glm_factor* f, const double* Omega, const double* beta, const double* u,
+                     const double* g_beta, const double* g_u, double tol, int32_t max_iter,
+                     double* dy, double* dOmega, double* dX, int32_t* info, int32_t* iters,
+                     hipStream_t s) {
+  const RedPlan& rp = f->rp;
+  double* yr = f->at<double>(rp.o_yr);
+  double* lb = f->at<double>(rp.o_lb);
+  if (g_u) {
+    if (int rc = timed_gemm1(f, g_u, yr, s)) return rc;
+  } else {
+    GLM_CHECK(launch_fill<double>(yr, rp.sumMrGK, 0.0, s));
+  }
+  int rc = solve_driver(f->sub, Omega, yr, g_beta, nullptr, tol, max_iter, lb,
+                        f->at<double>(rp.o_ur), nullptr, info, iters, s);
+  if (rc != GLM_OK) return rc;
+  if ((rc = red_full_u(f, Omega, g_u, lb, dy, s))) return rc;
+  GLM_CHECK(launch_red_grad(f->at<RedDesc>(rp.o_desc), rp.B, rp.maxM, f->sub->d_inst(),
+                            f->sub->at<int>(f->sub->p.o_colblk), dy, u, beta, lb,
+                            f->at<double>(rp.o_Zp), dOmega, dX, s));
+  GLM_CHECK(hipStreamSynchronize(s));
+  f->stats = f->sub->stats;
   return GLM_OK;
 }
 
@@ -1266,7 +1360,9 @@ int glm_gls_backward(glm_factor* f, const double* Omega, const double* beta, con
                      hipStream_t stream) {
   if (!f || !Omega || !beta || !u || !g_beta || !dy) return GLM_EINVAL;
   if (!(tol >= 0.0)) return GLM_EINVAL;
-  if (f->reduced) return GLM_EUNSUPPORTED;
+  if (f->reduced)
+    return backward_reduced(f, Omega, beta, u, g_beta, g_u, tol, max_iter, dy, dOmega, dX,
+                            info, iters, stream);
   const Plan& p = f->p;
   double* lb = f->at<double>(p.o_lb);
   // adjoint system [Sigma X; X^T 0][l_u; l_beta] = [g_u; g_beta] (restriction rows: 0)
@@ -1348,7 +1444,7 @@ int glm_profile_read(glm_factor* f, int kernel_id, int64_t* launches, double* to
   }
   f->ev_used.clear();
   if (f->reduced) {
-    // block-reflector applies: bytes counted on the host when launched
+    // Q1^T Y products: bytes counted on the host when launched
     if (launches) *launches = f->prof_launch[2];
     if (total_ms) *total_ms = f->prof_ms[2];
     if (total_bytes) *total_bytes = f->prof_bytes_host;

@@ -95,8 +95,10 @@ struct RedDesc {
   int M, n, G, K, Mr;
   int kr;          // reflectors: min(M, n)
   int rhs0;        // first (instance, rhs) index
-  int pad;
-  int64_t w_off;   // W copy: reflectors and R (M x n, row-major)
+  int inst;        // batch index of the instance
+  int64_t w_off;   // W copy: reflectors and R (M x n, row-major); also X and dX
+  int64_t q1_off;  // Q1 = Q [I; 0] (M x Mr)
+  int64_t b_off;   // beta-like (n x K)
   int64_t v_off;   // full vectors (M x G x K)
   int64_t xr_off;  // reduced regressors (Mr x n)
   int64_t vr_off;  // reduced vectors (Mr x G x K)
@@ -104,7 +106,13 @@ struct RedDesc {
   int64_t t_off;   // block-reflector factors T (panels x 32 x 32)
   int64_t om_off;  // Omega (G x G)
   int64_t zp_off;  // partial products V^T C of the row segments
-                   // (ceil(M / RED_SEG) x 32 x max(n, G K))
+                   // (ceil(M / RED_SEG) x max(32 (n + 1), G G)), also the
+                   // per-segment dOmega partials of the reverse mode
+};
+
+// One 64 x 64 output tile of a batched product with Q1 (inst < 0: padding).
+struct GemmTile {
+  int inst, i0, j0, pad;
 };
 constexpr int RED_PANEL = 32;    // columns per Householder panel
 constexpr int RED_SEG = 512;     // rows per workgroup of a block-reflector apply
@@ -221,13 +229,26 @@ hipError_t launch_update_c(const InstDesc* insts, int B, const RhsState* st,
 hipError_t launch_red_panel(const RedDesc* d, int B, int panel, double* W, double* tau,
                            double* T, hipStream_t s);
 hipError_t launch_red_apply(const RedDesc* d, int B, int panel, const double* W,
-                           const double* T, double* C, double* Zp, int target_w, int trans,
+                           const double* T, double* C, double* Zp, int target_q1, int trans,
                            int maxcols, int maxrows, hipStream_t s);
-hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, const double* Yt,
-                             double* Xr, double* yr, hipStream_t s);
-hipError_t launch_red_tail(const RedDesc* d, int B, int maxM, const double* Om, double* Oinv,
-                          const double* Yt, const double* ur, double* u, int32_t* info,
-                          hipStream_t s);
+hipError_t launch_red_qinit(const RedDesc* d, int B, double* Q1, hipStream_t s);
+hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, double* Xr,
+                             hipStream_t s);
+hipError_t launch_red_gemm_tn(const RedDesc* d, const GemmTile* tiles, int ntiles,
+                             const double* Q1, const double* Y, double* Yr, hipStream_t s);
+hipError_t launch_red_ginv(const RedDesc* d, int B, const double* Om, double* A, double* Og,
+                          int* sing, hipStream_t s);
+hipError_t launch_red_u(const RedDesc* d, int B, int chunks, const InstDesc* sinst,
+                       const BlockDesc* sblk, const double* X, const double* beta,
+                       const double* Y, const double* Og, double* U, hipStream_t s);
+hipError_t launch_red_singular(const RedDesc* d, int B, int chunks, const GemmTile* tiles2,
+                              int ntiles2, const int* sing, const double* Om, const double* Og,
+                              const double* Q1, const double* Ur, double* D, double* U,
+                              hipStream_t s);
+hipError_t launch_red_grad(const RedDesc* d, int B, int maxM, const InstDesc* sinst,
+                          const int* colblk, const double* L, const double* U,
+                          const double* beta, const double* lb, double* part, double* dOm,
+                          double* dX, hipStream_t s);
 hipError_t launch_grad(const InstDesc* insts, const TileDesc* tiles, int ntiles, int B,
                        const int* colblk, const double* L, const double* U,
                        const double* beta, const double* lb, double* part, double* dOm,

@@ -142,11 +142,16 @@ def test_reduced_workspace_and_flag_checks():
     assert rc == _lib.GLM_EWORKSPACE and not out.value
 
 
-def test_reduction_needs_at_most_64_equations():
+def test_reduction_takes_the_unreduced_limits():
+    """The reduction has no equation limit of its own: 65 and 256 equations
+    are planned like the unreduced problem, and the reduced workspace holds
+    Q1 (M x min(M, n + 1)) next to the copy of W."""
     from paper_2510_14471_amd import _lib
-    s = _shape([65], [200], [1], [1] * 65)
-    assert _lib.glm_workspace_bytes(s, _lib.GLM_FP64) > 0
-    assert _lib.glm_workspace_bytes(s, _lib.GLM_FP64 | _lib.GLM_REDUCED) == 0
+    for G in (65, 256):
+        s = _shape([G], [400], [1], [1] * G)
+        full = _lib.glm_workspace_bytes(s, _lib.GLM_FP64)
+        red = _lib.glm_workspace_bytes(s, _lib.GLM_FP64 | _lib.GLM_REDUCED)
+        assert full > 0 and red > 8 * 400 * (G + G + 1)
 
 
 @pytest.mark.parametrize("name", sorted(__import__("pass_cases").CASES))

@@ -27,11 +27,11 @@ def glmlib():
     return glm
 
 
-def solve(glm, insts, precision, tol=1e-12, max_iter=0):
-    print(f"[case] {precision} B={len(insts)} G={[i.G for i in insts][:4]} "
+def solve(glm, insts, precision, tol=1e-12, max_iter=0, reduce=False):
+    print(f"[case] {precision} reduce={reduce} B={len(insts)} G={[i.G for i in insts][:4]} "
           f"M={[i.M for i in insts][:4]} K={insts[0].K} k={insts[0].kc}", flush=True)
     lay, d = glm.pack_instances(insts)
-    s = glm.SURSolver(lay, precision)
+    s = glm.SURSolver(lay, precision, reduce=reduce)
     s.factor(d["X"], d["Rc"])
     beta, u, _, info, iters = s.solve(d["Omega"], d["y"], d["r"], tol=tol, max_iter=max_iter)
     torch.cuda.synchronize()
@@ -74,10 +74,11 @@ def test_batched_workload_all_pairs_and_identities(glmlib, precision):
 
 # -- one large SUR (G = 50, M = 10,000) ------------------------------------------------
 
+@pytest.mark.parametrize("reduce", [False, True], ids=["full", "reduced"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_large_single_sur(glmlib, precision):
+def test_large_single_sur(glmlib, precision, reduce):
     insts = list(synth.config1())
-    out = solve(glmlib, insts, precision)
+    out = solve(glmlib, insts, precision, reduce=reduce)
     beta_o, U_o = gls.sur_gls(insts[0])
     assert out["info"][0][0] in (0, 1)
     assert rel_err(out["beta"][0], beta_o) <= TOL
@@ -86,10 +87,13 @@ def test_large_single_sur(glmlib, precision):
 
 # -- singular Omega of rank G - 2 with 10 cross-equation restrictions -----------------
 
+@pytest.mark.parametrize("reduce", [False, True], ids=["full", "reduced"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_singular_restricted_workload(glmlib, precision):
+def test_singular_restricted_workload(glmlib, precision, reduce):
+    """G = 100, M = 50,000, rank G - 2, ten restrictions; also through the
+    model reduction (1,751 rotated rows instead of 50,000)."""
     inst = list(synth.config4())[0]
-    out = solve(glmlib, [inst], precision)
+    out = solve(glmlib, [inst], precision, reduce=reduce)
     beta_o, _, SU_o = gls.sur_solution(inst)
     beta = out["beta"][0]
     SU = np.einsum("tjk,ji->tik", out["u"][0], inst.Omega)
@@ -103,15 +107,17 @@ def test_singular_restricted_workload(glmlib, precision):
 
 # -- differentiation workload (G = 20, M = 20,000) ------------------------------------
 
+@pytest.mark.parametrize("reduce", [False, True], ids=["full", "reduced"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_differentiation_workload(glmlib, precision):
+def test_differentiation_workload(glmlib, precision, reduce):
     """dL/dy, dL/dOmega, dL/dX of L = 1/2 ||b - beta_true||^2 + the Gaussian
-    negative log-likelihood in Omega, through the autograd binding: against
-    the oracle's dense reference gradient, and against central finite
-    differences of the oracle's loss (h = 1e-6) on 200 random coordinates."""
+    negative log-likelihood in Omega, through the autograd binding (also
+    through the model reduction): against the oracle's dense reference
+    gradient, and against central finite differences of the oracle's loss
+    (h = 1e-6) on 200 random coordinates."""
     inst = list(synth.config3())[0]
     lay, d = glmlib.pack_instances([inst])
-    s = glmlib.SURSolver(lay, precision)
+    s = glmlib.SURSolver(lay, precision, reduce=reduce)
     X = d["X"].clone().requires_grad_(True)
     Om = d["Omega"].clone().requires_grad_(True)
     y = d["y"].clone().requires_grad_(True)
