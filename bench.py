@@ -1,13 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark: batched SUR GLS solves/s, mixed precision vs plain FP64 PCG-Aug.
 
-Workload: 512 independent SUR instances (G ~ U{4..32}, M ~ U{500..5000},
-n_i ~ U{3..20}, K = 16 right-hand sides each; X_i intercept + N(0,1),
-Omega = A A^T + 0.1 I), seeded synthetic data drawn on the host and resident
-in HBM before timing.  One step = factor (batched Householder QR) + solve of
-all 8,192 (instance, rhs) pairs.  `value` is the mixed-precision throughput;
-the FP64 path is timed on the same inputs and both are checked against the
-CPU oracle on a sample of instances at <= 1e-10 relative error.
+Headline workload: 512 independent SUR instances (G ~ U{4..32},
+M ~ U{500..5000}, n_i ~ U{3..20}, K = 16 right-hand sides each; X_i intercept
++ N(0,1), Omega = A A^T + 0.1 I), seeded synthetic data drawn on the host and
+resident in HBM before timing.  One step = the model reduction (QR of
+W = [X_1 ... X_G], Q1^T Y) + the per-block QR of the reduced problem + the
+solve of all 8,192 (instance, rhs) pairs + u of the full model.  `value` is
+the mixed-precision throughput; the FP64 path is timed on the same inputs,
+both without the reduction too, and every run is checked against the CPU
+oracle on a sample of instances at <= 1e-10 relative error.
+
+The timed steps run with kernel profiling off; one more step with profiling
+on (outside the timed region) gives the HIP-event durations and algorithmic
+bytes of the projection passes for the roofline.  The single large SUR
+(G = 50, M = 1e4), the differentiation workload (G = 20, M = 2e4) and the
+singular, restricted workload (G = 100, M = 5e4, rank G - 2, 10 restrictions)
+are measured the same way through the model reduction (`configs`).
 
 Prints one JSON line.
 """
@@ -16,6 +25,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -28,9 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE, WRITE_SIZE, calibrated against a plain copy kernel); valid only
 # for the kernel sources it was taken from
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_proj_sur_batch512_k16.json")
-KERNEL_SOURCES = ["paper_2510_14471_amd/csrc/proj.hip", "paper_2510_14471_amd/csrc/api.hip",
-                  "paper_2510_14471_amd/csrc/glm_internal.h", "paper_2510_14471_amd/csrc/reduce.hip",
-                  "paper_2510_14471_amd/csrc/qr_panel.h"]
+KERNEL_SOURCES = ["paper_2510_14471_amd/csrc/proj.hip",
+                  "paper_2510_14471_amd/csrc/glm_internal.h"]
 PASS_NAMES = {0: "k_proj_a<float> (pass A: u <- g + mu u, B = U Omega, d = u.B, T += Q^T B)",
               1: "k_proj_b<float> (pass B: g -= (lambda/alpha)(B - Q T), w -= lambda u, c = g.g)",
               2: "k_red_gemm_tn (model reduction: reduced responses Y_red = Q1^T Y, "
@@ -47,6 +56,47 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
+class Runner:
+    """Times factor + solve of one packed workload on one solver."""
+
+    def __init__(self, glm, torch, lay, d, tol):
+        self.glm, self.torch, self.lay, self.d, self.tol = glm, torch, lay, d, tol
+
+    def step(self, s):
+        s.factor(self.d["X"], self.d["Rc"])
+        beta, u, _, info, _ = s.solve(self.d["Omega"], self.d["y"], self.d["r"], tol=self.tol)
+        return beta, u, info, s.stats()
+
+    def run(self, prec, reduce, steps, warmup, profile):
+        torch = self.torch
+        s = self.glm.SURSolver(self.lay, prec, reduce=reduce)
+        for _ in range(warmup):
+            self.step(s)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        iters = outer = 0
+        for _ in range(steps):
+            beta, u, info, st = self.step(s)
+            iters += st["pcg_iterations"]
+            outer += st["outer_steps"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        prof = None
+        if profile:
+            # one more step with the kernel timers on, outside the timed region
+            s.profile(True)
+            self.step(s)
+            torch.cuda.synchronize()
+            prof = {k: s.profile_read(k) for k in PASS_NAMES}
+            s.profile(False)
+        ws = s.workspace_bytes
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        return dict(dt=dt, iters=iters, outer=outer, beta=beta, u=u, info=info, prof=prof,
+                    ws=ws, steps=steps)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +110,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-unreduced", action="store_true",
                     help="skip the runs without the model reduction")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the single large, differentiation and singular workloads")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -77,34 +129,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t0 = time.time()
-    batch = synth.config2(B=args.instances)
-    insts = list(batch)
+    insts = list(synth.config2(B=args.instances))
     log(f"generated {len(insts)} instances in {time.time() - t0:.1f}s")
     lay, d = glm.pack_instances(insts)
     torch.cuda.synchronize()
     n_solves = lay.n_rhs
     log(f"packed: X {d['X'].numel() * 8 / 1e9:.2f} GB, y {d['y'].numel() * 8 / 1e9:.2f} GB")
-
-    def timed(solver, steps, profile=False):
-        if profile:
-            solver.profile(True)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        iters = 0
-        outer = 0
-        for _ in range(steps):
-            solver.factor(d["X"])
-            beta, u, _, info, _ = solver.solve(d["Omega"], d["y"], tol=args.tol)
-            st = solver.stats()
-            iters += st["pcg_iterations"]
-            outer += st["outer_steps"]
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        prof = None
-        if profile:
-            prof = {k: solver.profile_read(k) for k in PASS_NAMES}
-            solver.profile(False)
-        return dt, iters, outer, beta, u, info, prof
+    runner = Runner(glm, torch, lay, d, args.tol)
 
     # the product path (model reduction: one QR of W, the iteration on n + 1
     # rotated rows) and the iteration on all M rows, each in mixed precision
@@ -117,27 +148,20 @@ def main():
     results = {}
     for prec, red in runs:
         key = prec + ("" if red else "_unreduced")
-        s = glm.SURSolver(lay, prec, reduce=red)
-        log(f"{key}: workspace {s.workspace_bytes / 1e9:.2f} GB")
-        for _ in range(args.warmup):
-            timed(s, 1)
-        dt, iters, outer, beta, u, info, prof = timed(s, args.steps, profile=(prec == "mixed"))
-        infos = info.cpu().numpy()
-        results[key] = dict(dt=dt, iters=iters, outer=outer, beta=beta, u=u,
-                            ok=int(np.sum((infos == 0) | (infos == 1))), prof=prof)
-        log(f"{key}: {args.steps} steps in {dt:.3f}s -> {n_solves * args.steps / dt:.1f} solves/s,"
-            f" {iters / args.steps:.0f} PCG iterations/step, outer {outer / args.steps:.1f},"
-            f" ok {results[key]['ok']}/{n_solves}")
-        s.close()
-        del s
-        torch.cuda.empty_cache()
+        r = runner.run(prec, red, args.steps, args.warmup, profile=(prec == "mixed"))
+        infos = r["info"].cpu().numpy()
+        r["ok"] = int(np.sum((infos == 0) | (infos == 1)))
+        results[key] = r
+        log(f"{key}: workspace {r['ws'] / 1e9:.2f} GB; {args.steps} steps in {r['dt']:.3f}s -> "
+            f"{n_solves * args.steps / r['dt']:.1f} solves/s, {r['iters'] / args.steps:.0f} PCG "
+            f"iterations/step, outer {r['outer'] / args.steps:.1f}, ok {r['ok']}/{n_solves}")
 
     # accuracy against the oracle on a sample of instances
     from oracle import gls as ogls
     errs = {}
     sample = list(range(0, len(insts), max(1, len(insts) // max(1, args.check))))[: args.check]
     ref = {b: ogls.sur_gls(insts[b]) for b in sample}
-    for prec, r in results.items():
+    for key, r in results.items():
         betas = glm.unpack(lay, r["beta"], "beta")
         us = glm.unpack(lay, r["u"], "u")
         eb = eu = 0.0
@@ -146,8 +170,8 @@ def main():
             for k in range(insts[b].K):
                 eb = max(eb, rel(betas[b][:, k], beta_o[:, k]))
                 eu = max(eu, rel(us[b][:, :, k], U_o[:, :, k]))
-        errs[prec] = (eb, eu)
-        log(f"{prec}: max rel err on {len(sample)} instances: beta {eb:.2e}, u {eu:.2e}")
+        errs[key] = (eb, eu)
+        log(f"{key}: max rel err on {len(sample)} instances: beta {eb:.2e}, u {eu:.2e}")
 
     mixed = results["mixed"]
     value = n_solves * args.steps / mixed["dt"]
@@ -166,7 +190,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"sur_batch{len(insts)}_K16: G~U{{4..32}}, M~U{{500..5000}}, "
                                "n_i~U{3..20}, Omega=AA^T+0.1I; step = model reduction (QR of "
-                               "W = [X_1..X_G], rotation of Y) + per-block QR + solve of all "
+                               "W = [X_1..X_G], Q1^T Y) + per-block QR + solve of all "
                                "(instance, rhs), u of the full model",
                    "instances": len(insts), "solves_per_step": n_solves, "tol": args.tol},
         "pcg_iterations_per_s": round(mixed["iters"] / mixed["dt"], 1),
@@ -181,24 +205,79 @@ def main():
         out["speedup_mixed_vs_fp64"] = round(value / v64, 3)
         out["fp64_pcg_iterations_per_s"] = round(f64["iters"] / f64["dt"], 1)
     if "mixed_unreduced" in results:
-        un = {"mixed_solves_per_s": round(n_solves * args.steps / results["mixed_unreduced"]["dt"], 2),
-              "pcg_iterations_per_s": round(results["mixed_unreduced"]["iters"] /
-                                            results["mixed_unreduced"]["dt"], 1)}
+        mu = results["mixed_unreduced"]
+        un = {"mixed_solves_per_s": round(n_solves * args.steps / mu["dt"], 2),
+              "pcg_iterations_per_s": round(mu["iters"] / mu["dt"], 1)}
         if "fp64_unreduced" in results:
             un["fp64_solves_per_s"] = round(n_solves * args.steps / results["fp64_unreduced"]["dt"], 2)
             un["speedup_mixed_vs_fp64"] = round(un["mixed_solves_per_s"] / un["fp64_solves_per_s"], 3)
-        rl = roofline(results["mixed_unreduced"]["prof"], reduced=False)
+        rl = roofline(mu["prof"], traffic_key="")
         if rl:
             un["roofline"] = rl[0]
         out["without_model_reduction"] = un
-    rl = roofline(mixed["prof"], reduced=True)
+    rl = roofline(mixed["prof"], traffic_key="r")
     if rl:
         out["roofline"], others = rl
         if others:
             out["roofline_other"] = others
+    del runner, d
+    torch.cuda.empty_cache()
+    if not args.no_configs:
+        out["configs"] = other_configs(glm, torch, synth, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def other_configs(glm, torch, synth, args):
+    """The single large SUR, the differentiation and the singular, restricted
+    workloads through the model reduction, mixed and FP64: solves/s (factor +
+    solve per step), PCG iterations/s, the dominant pass's roofline and the
+    error against the oracle."""
+    import numpy as np
+    from oracle import gls as ogls
+    out = {}
+    specs = [("sur_large_G50_M10000", synth.config1),
+             ("sur_grad_G20_M20000", synth.config3),
+             ("sur_singular_restricted_G100_M50000_k10", synth.config4)]
+    for name, make in specs:
+        inst = list(make())[0]
+        lay, d = glm.pack_instances([inst])
+        t = time.perf_counter()
+        beta_o, U_o, SU_o = ogls.sur_solution(inst)
+        t_oracle = time.perf_counter() - t
+        runner = Runner(glm, torch, lay, d, args.tol)
+        entry = {"oracle_s": round(t_oracle, 2)}
+        for prec in ("mixed", "fp64"):
+            r = runner.run(prec, True, 1, 1, profile=True)
+            beta = glm.unpack(lay, r["beta"], "beta")[0]
+            u = glm.unpack(lay, r["u"], "u")[0]
+            if U_o is not None:
+                eu = rel(u, U_o)
+            else:
+                eu = rel(np.einsum("tjk,ji->tik", u, inst.Omega), SU_o)
+            info = int(r["info"].cpu().numpy()[0])
+            e = {"solves_per_s": round(1.0 / r["dt"], 3), "ms_per_step": round(1000 * r["dt"], 2),
+                 "pcg_iterations": int(r["iters"]),
+                 "pcg_iterations_per_s": round(r["iters"] / r["dt"], 1),
+                 "outer_steps": int(r["outer"]), "info": info,
+                 "max_rel_err": {"beta": rel(beta, beta_o),
+                                 ("u" if U_o is not None else "Sigma_u"): eu}}
+            rl = roofline(r["prof"], traffic_key=None, names={
+                0: f"k_proj_a<{'float' if prec == 'mixed' else 'double'}>",
+                1: f"k_proj_b<{'float' if prec == 'mixed' else 'double'}>",
+                2: PASS_NAMES[2]})
+            if rl:
+                e["roofline"] = rl[0]
+            entry[prec] = e
+            log(f"{name} {prec}: {1000 * r['dt']:.1f} ms/step, {r['iters']} PCG iterations, "
+                f"beta err {e['max_rel_err']['beta']:.2e}")
+        entry["speedup_mixed_vs_fp64"] = round(entry["mixed"]["solves_per_s"] /
+                                               entry["fp64"]["solves_per_s"], 3)
+        out[name] = entry
+        del runner, d
+        torch.cuda.empty_cache()
+    return out
 
 
 def kernel_sources_sha256():
@@ -210,9 +289,11 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(pass_id, reduced):
+def measured_traffic(key):
     """HBM bytes per launch of the timed kernel from the committed counter
     summary, or None when it is missing or the kernel sources changed since."""
+    if key is None:
+        return None
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -220,29 +301,32 @@ def measured_traffic(pass_id, reduced):
         return None
     if t.get("sources_sha256") != kernel_sources_sha256():
         return None
-    k = t.get("passes", {}).get(("r" if reduced else "") + str(pass_id))
+    k = t.get("passes", {}).get(key)
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def roofline(prof, reduced):
+def roofline(prof, traffic_key, names=None):
     """(roofline of the kernel with the most timed milliseconds, the others)."""
+    names = names or PASS_NAMES
     if not prof:
         return None
-    timed_ids = [k for k in PASS_NAMES if prof.get(k) and prof[k][0] and prof[k][1] > 0]
+    timed_ids = [k for k in names if prof.get(k) and prof[k][0] and prof[k][1] > 0]
     if not timed_ids:
         return None
     kid = max(timed_ids, key=lambda k: prof[k][1])
     n_l, ms, by = prof[kid]
     ach = (by / n_l) / (ms / n_l * 1e-3) / 1e9
     main_rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kid, reduced),
-               "kernel": PASS_NAMES[kid], "launches": n_l, "avg_us": round(1000 * ms / n_l, 2),
+               "frac": round(ach / HBM_PEAK_GBS, 4),
+               "traffic": measured_traffic(None if traffic_key is None
+                                           else traffic_key + str(kid)),
+               "kernel": names[kid], "launches": n_l, "avg_us": round(1000 * ms / n_l, 2),
                "alg_bytes_per_launch": round(by / n_l)}
     others = []
     for k in timed_ids:
         if k != kid:
             n2, ms2, by2 = prof[k]
-            others.append({"kernel": PASS_NAMES[k], "launches": n2,
+            others.append({"kernel": names[k], "launches": n2,
                            "avg_us": round(1000 * ms2 / n2, 2),
                            "achieved": round((by2 / n2) / (ms2 / n2 * 1e-3) / 1e9, 1),
                            "share_of_timed_ms": round(ms2 / sum(prof[j][1] for j in timed_ids), 3)})
@@ -250,29 +334,51 @@ def roofline(prof, reduced):
     return main_rl, others
 
 
-def cpu_baseline(insts, budget_s):
-    """The oracle (textbook SUR GLS by Cholesky, NumPy/LAPACK) on the host cores,
-    on the first instances of the same workload until ~budget_s of work."""
-    import numpy as np
-    from oracle import gls as ogls
+def cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
     except Exception:
-        cores = os.cpu_count() or 1
+        pass
+    return "unknown"
+
+
+def _oracle_rate(insts, budget_s):
+    from oracle import gls as ogls
     t = time.perf_counter()
-    solves = 0
-    done = 0
+    solves = done = 0
     for inst in insts:
         ogls.sur_gls(inst)
         solves += inst.K
         done += 1
         if time.perf_counter() - t > budget_s:
             break
-    dt = time.perf_counter() - t
-    return {"value": round(solves / dt, 2), "unit": "solves/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"first {done} of {len(insts)} instances ({solves} solves), {dt:.1f}s"}
+    return solves, done, time.perf_counter() - t
+
+
+def cpu_baseline(insts, budget_s):
+    """The oracle (textbook SUR GLS by Cholesky, NumPy/LAPACK) on the host
+    cores, on the first instances of the same workload until ~budget_s of
+    work, with every BLAS thread, then with one."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threadpool_limits = None
+        cores = os.cpu_count() or 1
+    solves, done, dt = _oracle_rate(insts, budget_s)
+    out = {"value": round(solves / dt, 2), "unit": "solves/s", "cores": int(cores),
+           "kind": "oracle", "cpu": cpu_model(), "logical_cpus": os.cpu_count(),
+           "sample": f"first {done} of {len(insts)} instances ({solves} solves), {dt:.1f}s, "
+                     f"{cores} BLAS threads"}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            s1, d1, t1 = _oracle_rate(insts, budget_s / 2)
+        out["single_thread"] = {"value": round(s1 / t1, 2), "unit": "solves/s",
+                                "sample": f"first {d1} instances ({s1} solves), {t1:.1f}s"}
+    return out
 
 
 if __name__ == "__main__":

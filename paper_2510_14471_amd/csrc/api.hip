@@ -472,7 +472,7 @@ namespace {
 // the reduction buffers, followed by the reduced problem's own workspace.
 struct RedPlan {
   int B = 0, maxpan = 0, maxn = 0, maxM = 0, maxMr = 0;
-  int uchunks = 0, dchunks = 0;   // row chunks of k_red_u and k_red_delta
+  int dchunks = 0;   // row chunks of k_red_delta
   std::vector<RedDesc> d;
   // the device copy of the descriptors, tallest instance first: every
   // reduction kernel takes its instance from its descriptor, so the order
@@ -551,7 +551,6 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     const int npan = (d.kr + RED_PANEL - 1) / RED_PANEL;
     const int P = d.G * d.K;
     const int rows = std::max(1, std::min(32, 4096 / P));
-    r.uchunks = std::max(r.uchunks, (d.M + rows - 1) / rows);
     r.dchunks = std::max(r.dchunks, (d.Mr + rows - 1) / rows);
     r.maxpan = std::max(r.maxpan, npan);
     r.maxn = std::max(r.maxn, n);
@@ -1158,7 +1157,7 @@ int red_full_u(glm_factor* f, const double* Omega, const double* Y, const double
   int* sing = f->at<int>(rp.o_sing);
   GLM_CHECK(launch_red_ginv(dd, rp.B, Omega, f->at<double>(rp.o_Ow), f->at<double>(rp.o_Og),
                             sing, s));
-  GLM_CHECK(launch_red_u(dd, rp.B, rp.uchunks, f->sub->d_inst(), f->sub->d_blk(), f->X, b, Y,
+  GLM_CHECK(launch_red_u(dd, rp.B, rp.maxM, f->sub->d_inst(), f->sub->d_blk(), f->X, b, Y,
                          f->at<double>(rp.o_Og), U, s));
   std::vector<int> hs(rp.B, 0);
   GLM_CHECK(hipMemcpyAsync(hs.data(), sing, 4 * (size_t)rp.B, hipMemcpyDeviceToHost, s));

@@ -238,7 +238,7 @@ hipError_t launch_red_gemm_tn(const RedDesc* d, const GemmTile* tiles, int ntile
                              const double* Q1, const double* Y, double* Yr, hipStream_t s);
 hipError_t launch_red_ginv(const RedDesc* d, int B, const double* Om, double* A, double* Og,
                           int* sing, hipStream_t s);
-hipError_t launch_red_u(const RedDesc* d, int B, int chunks, const InstDesc* sinst,
+hipError_t launch_red_u(const RedDesc* d, int B, int maxM, const InstDesc* sinst,
                        const BlockDesc* sblk, const double* X, const double* beta,
                        const double* Y, const double* Og, double* U, hipStream_t s);
 hipError_t launch_red_singular(const RedDesc* d, int B, int chunks, const GemmTile* tiles2,

@@ -352,7 +352,7 @@ k_red_gemm_tn(const RedDesc* __restrict__ descs, const GemmTile* __restrict__ ti
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
     if (kc + 1 < nk) load((kc + 1) * GKC);
-#pragma unroll
+#pragma unroll 4
     for (int k = 0; k < GKC; ++k) {
       const double2 a01 = *reinterpret_cast<const double2*>(&As[buf][k][ty * 4]);
       const double2 a23 = *reinterpret_cast<const double2*>(&As[buf][k][ty * 4 + 2]);
@@ -433,7 +433,7 @@ k_red_gemm_nn(const RedDesc* __restrict__ descs, const GemmTile* __restrict__ ti
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
     if (kc + 1 < nk) load((kc + 1) * GKC);
-#pragma unroll
+#pragma unroll 4
     for (int k = 0; k < GKC; ++k) {
       const double2 a01 = *reinterpret_cast<const double2*>(&As[buf][k][ty * 4]);
       const double2 a23 = *reinterpret_cast<const double2*>(&As[buf][k][ty * 4 + 2]);
@@ -581,10 +581,35 @@ k_red_ginv(const RedDesc* __restrict__ descs, const double* __restrict__ Om,
   if (tid == 0) sing[d.inst] = (r < G) ? 1 : 0;
 }
 
-// U = (Y - [X_i beta_i]) Omega^g, RTR rows per workgroup (instance, chunk);
-// Y may be null (zero).  The blocks' columns come from the reduced problem's
-// block table (the same blocks).
+// U = (Y - [X_i beta_i]) Omega^g.  Workgroup (instance, URC rows), taken in
+// sub-chunks of ur rows whose X and Y rows are staged in LDS with coalesced
+// loads; Omega^g sits in the same 64 KB of LDS first when G <= 64.  The
+// shape limits keep one row within the rest: G <= 64 has G K <= 1024 and
+// n <= 2048; G > 64 has n + G K <= 1024 + 4096.  Y may be null (zero).  The
+// blocks' columns come from the reduced problem's block table (the same
+// blocks).
 constexpr int RTR = 32;
+constexpr int URC = 64;
+constexpr int ULDS = 8192;     // doubles of LDS: Omega^g (G <= 64), then X and Y rows
+
+// dst[e] = src[e] (src may be null: zeros) for e < count by the workgroup,
+// eight loads in flight per thread
+__device__ __forceinline__ void stage_rows(double* __restrict__ dst,
+                                           const double* __restrict__ src, int count) {
+  for (int base = 0; base < count; base += 8 * QNT) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = base + q * QNT + (int)threadIdx.x;
+      v[q] = (src && e < count) ? src[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = base + q * QNT + (int)threadIdx.x;
+      if (e < count) dst[e] = v[q];
+    }
+  }
+}
 
 __global__ void __launch_bounds__(QNT)
 k_red_u(const RedDesc* __restrict__ descs, const InstDesc* __restrict__ sinst,
@@ -593,30 +618,64 @@ k_red_u(const RedDesc* __restrict__ descs, const InstDesc* __restrict__ sinst,
         const double* __restrict__ Og, double* __restrict__ U) {
   const RedDesc d = descs[blockIdx.x];
   const int G = d.G, K = d.K, P = G * K, n = d.n, tid = threadIdx.x;
-  const int rows = max(1, min(RTR, 4096 / P));
-  const int t0 = blockIdx.y * rows;
-  if (t0 >= d.M) return;
-  const int t1 = min(d.M, t0 + rows);
-  __shared__ double Es[4096];
+  const int tb = blockIdx.y * URC;
+  if (tb >= d.M) return;
+  const int te = min(d.M, tb + URC);
+  __shared__ double sm[ULDS];
+  __shared__ int s_col[256], s_ni[256];
   const BlockDesc* bd = sblk + sinst[d.inst].blk0;
-  const double* og = Og + d.om_off;
-  const double* bb = beta + d.b_off;
-  for (int e = tid; e < (t1 - t0) * P; e += QNT) {
-    const int tt = e / P, rem = e - tt * P, g = rem / K, k = rem - g * K;
-    const int64_t t = t0 + tt;
-    const BlockDesc b = bd[g];
-    const double* xr = X + d.w_off + t * n + b.col;
-    double s = Y ? Y[d.v_off + t * P + rem] : 0.0;
-    for (int c = 0; c < b.ni; ++c) s -= xr[c] * bb[(int64_t)(b.col + c) * K + k];
-    Es[e] = s;
+  for (int g = tid; g < G; g += QNT) {
+    s_col[g] = bd[g].col;
+    s_ni[g] = bd[g].ni;
   }
-  __syncthreads();
-  for (int e = tid; e < (t1 - t0) * P; e += QNT) {
-    const int tt = e / P, rem = e - tt * P, i = rem / K, k = rem - i * K;
-    const double* er = Es + tt * P + k;
-    double s = 0.0;
-    for (int g = 0; g < G; ++g) s += er[g * K] * og[g * G + i];
-    U[d.v_off + (int64_t)(t0 + tt) * P + rem] = s;
+  const double* og = Og + d.om_off;
+  const bool og_lds = G <= 64;
+  if (og_lds)
+    for (int e = tid; e < G * G; e += QNT) sm[e] = og[e];
+  const double* ogp = og_lds ? sm : og;
+  const double* bb = beta + d.b_off;
+  double* Xs = sm + (og_lds ? G * G : 0);
+  const int cap = ULDS - (og_lds ? G * G : 0);
+  const int ur = max(1, min(8, cap / (n + P)));
+  double* Es = Xs + ur * n;
+  for (int t0 = tb; t0 < te; t0 += ur) {
+    const int nr = min(ur, te - t0);
+    __syncthreads();
+    stage_rows(Xs, X + d.w_off + (int64_t)t0 * n, nr * n);
+    stage_rows(Es, Y ? Y + d.v_off + (int64_t)t0 * P : nullptr, nr * P);
+    __syncthreads();
+    // fitted values: a thread per (equation g, rhs k) pair over the
+    // sub-chunk's rows, the block's beta column eight loads at a time
+    for (int pq = tid; pq < P; pq += QNT) {
+      const int g = pq / K, k = pq - g * K, col = s_col[g], ni = s_ni[g];
+      const double* br = bb + (int64_t)col * K + k;
+      double acc[8];
+#pragma unroll
+      for (int tt = 0; tt < 8; ++tt) acc[tt] = 0.0;
+      for (int c0 = 0; c0 < ni; c0 += 8) {
+        double bv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bv[q] = (c0 + q < ni) ? br[(int64_t)(c0 + q) * K] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (c0 + q >= ni) break;
+#pragma unroll
+          for (int tt = 0; tt < 8; ++tt)
+            if (tt < nr) acc[tt] += Xs[tt * n + col + c0 + q] * bv[q];
+        }
+      }
+#pragma unroll
+      for (int tt = 0; tt < 8; ++tt)
+        if (tt < nr) Es[tt * P + pq] -= acc[tt];
+    }
+    __syncthreads();
+    for (int e = tid; e < nr * P; e += QNT) {
+      const int tt = e / P, rem = e - tt * P, i = rem / K, k = rem - i * K;
+      const double* er = Es + tt * P + k;
+      double s = 0.0;
+      for (int g = 0; g < G; ++g) s += er[g * K] * ogp[g * G + i];
+      U[d.v_off + (int64_t)t0 * P + e] = s;
+    }
   }
 }
 
@@ -767,12 +826,12 @@ hipError_t launch_red_ginv(const RedDesc* d, int B, const double* Om, double* A,
   return hipGetLastError();
 }
 
-hipError_t launch_red_u(const RedDesc* d, int B, int chunks, const InstDesc* sinst,
+hipError_t launch_red_u(const RedDesc* d, int B, int maxM, const InstDesc* sinst,
                        const BlockDesc* sblk, const double* X, const double* beta,
                        const double* Y, const double* Og, double* U, hipStream_t s) {
-  if (B <= 0 || chunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_red_u, dim3(B, chunks), dim3(QNT), 0, s, d, sinst, sblk, X, beta, Y,
-                     Og, U);
+  if (B <= 0 || maxM <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_red_u, dim3(B, (maxM + URC - 1) / URC), dim3(QNT), 0, s, d, sinst, sblk,
+                     X, beta, Y, Og, U);
   return hipGetLastError();
 }
 
