@@ -449,6 +449,32 @@ struct EventPair {
   int kid;
 };
 
+// Launch arguments that differ between the captured iteration chunks of one
+// handle (everything else is fixed by the plan and the workspace).
+struct GraphKey {
+  size_t elem;
+  const void *Q, *Om, *y, *w;
+  double tol;
+  int stall, maxit_cap;
+  bool operator==(const GraphKey& o) const {
+    return elem == o.elem && Q == o.Q && Om == o.Om && y == o.y && w == o.w && tol == o.tol &&
+           stall == o.stall && maxit_cap == o.maxit_cap;
+  }
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+};
+
+// Iteration chunks run as HIP graphs unless GLM_GRAPHS=0 in the environment.
+bool graphs_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("GLM_GRAPHS");
+    return !(v && v[0] == '0');
+  }();
+  return on;
+}
+
 // The pass configuration of a plan in the glm_stats fields (index 0: FP32
 // inner solves of the mixed path, -1 when there are none; 1: FP64 solves).
 void pass_stats(const Plan& p, glm_stats* st) {
@@ -471,7 +497,7 @@ namespace {
 // equations and blocks with min(M, n + 1) observations) and the layout of
 // the reduction buffers, followed by the reduced problem's own workspace.
 struct RedPlan {
-  int B = 0, maxpan = 0, maxn = 0, maxM = 0, maxMr = 0;
+  int B = 0, maxpan = 0, maxn = 0, maxM = 0, maxMr = 0, maxseg = 0;
   int dchunks = 0;   // row chunks of k_red_delta
   std::vector<RedDesc> d;
   // the device copy of the descriptors, tallest instance first: every
@@ -484,9 +510,10 @@ struct RedPlan {
   std::vector<int32_t> G, M, K, k, n;
   glm_shape sub{};
   int64_t sumMn = 0, sumMGK = 0, sumMrn = 0, sumMrGK = 0, sumn = 0, sumT = 0, sumG2 = 0,
-          sumZp = 0, sumMMr = 0, sumnK = 0;
+          sumZp = 0, sumMMr = 0, sumnK = 0, sumLeaf = 0;
   double gemm1_bytes = 0.0;   // algorithmic bytes of one Q1^T Y over the batch
-  size_t o_desc = 0, o_W = 0, o_tau = 0, o_T = 0, o_Q1 = 0, o_Xr = 0, o_yr = 0, o_ur = 0,
+  size_t o_desc = 0, o_W = 0, o_tau = 0, o_T = 0, o_Tleaf = 0, o_Stk = 0, o_Q1 = 0, o_Xr = 0,
+         o_yr = 0, o_ur = 0,
          o_dd = 0, o_Og = 0, o_Ow = 0, o_sing = 0, o_t1 = 0, o_t2 = 0, o_Zp = 0, o_lb = 0,
          o_sub = 0, sub_bytes = 0, total = 0;
 };
@@ -549,6 +576,11 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     d.om_off = om;
     d.zp_off = r.sumZp;
     const int npan = (d.kr + RED_PANEL - 1) / RED_PANEL;
+    d.nseg0 = (d.M + RED_LEAF - 1) / RED_LEAF;
+    d.leaf_off = r.sumLeaf;
+    d.stk_off = r.sumLeaf;
+    r.sumLeaf += (int64_t)npan * d.nseg0 * RED_PANEL * RED_PANEL;
+    r.maxseg = std::max(r.maxseg, d.nseg0);
     const int P = d.G * d.K;
     const int rows = std::max(1, std::min(32, 4096 / P));
     r.dchunks = std::max(r.dchunks, (d.Mr + rows - 1) / rows);
@@ -564,8 +596,7 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     r.sumMrGK += (int64_t)d.Mr * P;
     r.sumn += n;
     r.sumT += (int64_t)npan * RED_PANEL * RED_PANEL;
-    r.sumZp += (int64_t)((d.M + RED_SEG - 1) / RED_SEG) *
-               std::max<int64_t>((int64_t)RED_PANEL * (n + 1), (int64_t)d.G * d.G);
+    r.sumZp += (int64_t)((d.M + RED_SEG - 1) / RED_SEG) * d.G * d.G;
     r.gemm1_bytes += 8.0 * ((double)d.M * d.Mr + (double)d.M * P + (double)d.Mr * P);
     om += (int64_t)d.G * d.G;
     r.sumG2 = om;
@@ -607,6 +638,8 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
   r.o_W = take(8 * r.sumMn);
   r.o_tau = take(8 * r.sumn);
   r.o_T = take(8 * r.sumT);
+  r.o_Tleaf = take(8 * r.sumLeaf);
+  r.o_Stk = take(8 * r.sumLeaf);
   r.o_Q1 = take(8 * r.sumMMr);
   r.o_Xr = take(8 * r.sumMrn);
   r.o_yr = take(8 * r.sumMrGK);
@@ -635,6 +668,12 @@ struct glm_factor {
   int* h_count = nullptr;   // pinned, or h_count_host when pinned memory is not wanted
   bool h_count_pinned = false;
   int h_count_host[4] = {0, 0, 0, 0};
+  // HIP graphs of the iteration chunks, keyed by their launch arguments, and
+  // the private stream they are captured on (never on the caller's stream,
+  // which may be the null stream)
+  bool use_graphs = false;
+  hipStream_t cap_stream = nullptr;
+  std::vector<GraphEntry> graphs;
   glm_stats stats{};
   bool prof = false;
   std::vector<EventPair> ev_used, ev_free;
@@ -821,31 +860,72 @@ int core_solve(glm_factor* f, const T* Q, const T* Om, const T* y, const double*
   for (const auto& in : p.inst) maxit_all = std::max<int64_t>(maxit_all, in.maxit);
   if (maxit_cap > 0) maxit_all = std::min<int64_t>(maxit_all, maxit_cap);
   PassLaunch<T> aa = pass_args<T>(f, Q, Om, y, w, g, u, false);
-  for (int64_t it = 0; it < maxit_all + 1; ++it) {
-    if (it % kPollEvery == 0) {
-      GLM_CHECK(launch_count(f->at<int>(p.o_icount), p.B, f->at<int>(p.o_count), s));
-      GLM_CHECK(hipMemcpyAsync(f->h_count, f->at<int>(p.o_count), sizeof(int),
-                               hipMemcpyDeviceToHost, s));
-      GLM_CHECK(hipStreamSynchronize(s));
-      if (log_on() && (it % (kPollEvery * 16) == 0 || *f->h_count == 0))
-        std::fprintf(stderr, "[glm %.3fs] %s pcg it %lld active rhs %d\n", now_s(),
-                     sizeof(T) == 8 ? "fp64" : "fp32", (long long)it, *f->h_count);
-      if (*f->h_count == 0) break;
-    }
-    if (int rc = run_pass_a<T>(f, aa, PASS_A_ITER, s)) return rc;
+  // one PCG iteration: pass A, the sum of its partials, lambda, pass B, mu and
+  // the stopping tests; every kernel reads the (instance, rhs) states, so an
+  // iteration after convergence does nothing
+  auto iteration = [&](hipStream_t st) -> int {
+    if (int rc = run_pass_a<T>(f, aa, PASS_A_ITER, st)) return rc;
     GLM_CHECK(launch_reduce_t<T>(f->d_inst(), f->d_tile(), f->d_active(),
                                  f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
                                  f->at<T>(p.o_Tpart), Tm,
-                                 p.cfg[sizeof(T) == 8].rowpass, s));
+                                 p.cfg[sizeof(T) == 8].rowpass, st));
     GLM_CHECK(launch_scalar_a<T>(f->d_inst(), f->d_tile(), f->d_active(), f->d_st(),
                                  f->at<double>(p.o_dpart), Tm, f->at<double>(p.o_Nb),
-                                 nullptr, p.B, 1, 1, s));
-    if (int rc = run_pass_b<T>(f, aa, PASS_B_ITER, s)) return rc;
+                                 nullptr, p.B, 1, 1, st));
+    if (int rc = run_pass_b<T>(f, aa, PASS_B_ITER, st)) return rc;
     GLM_CHECK(launch_scalar_b(f->d_inst(), f->d_active(), f->at<int>(p.o_icount), f->d_st(),
                               f->at<double>(p.o_cpart), f->at<double>(p.o_alpha), Tm,
                               t_double, gc, uc, wc, nullptr, p.B, 1, tol, stall, maxit_cap,
-                              s));
+                              st));
     f->launches += 3;
+    return GLM_OK;
+  };
+  // the kPollEvery iterations between two polls, captured once per argument
+  // set in a HIP graph and replayed (not while the kernel timers run, whose
+  // events sit between the launches)
+  hipGraphExec_t chunk = nullptr;
+  if (f->use_graphs && !f->prof) {
+    const GraphKey key{sizeof(T), Q, Om, y, w, tol, stall, maxit_cap};
+    for (const auto& ge : f->graphs)
+      if (ge.key == key) chunk = ge.exec;
+    if (!chunk) {
+      if (!f->cap_stream)
+        GLM_CHECK(hipStreamCreateWithFlags(&f->cap_stream, hipStreamNonBlocking));
+      GLM_CHECK(hipStreamBeginCapture(f->cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc = GLM_OK;
+      const int l0 = f->launches;
+      for (int j = 0; j < kPollEvery && rc == GLM_OK; ++j) rc = iteration(f->cap_stream);
+      f->launches = l0;
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(f->cap_stream, &graph);
+      if (rc != GLM_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc != GLM_OK ? rc : GLM_EHIP;
+      }
+      const hipError_t ei = hipGraphInstantiate(&chunk, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return GLM_EHIP;
+      f->graphs.push_back(GraphEntry{key, chunk});
+    }
+  }
+  for (int64_t it = 0; it < maxit_all + 1; it += kPollEvery) {
+    GLM_CHECK(launch_count(f->at<int>(p.o_icount), p.B, f->at<int>(p.o_count), s));
+    GLM_CHECK(hipMemcpyAsync(f->h_count, f->at<int>(p.o_count), sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    GLM_CHECK(hipStreamSynchronize(s));
+    if (log_on() && (it % (kPollEvery * 16) == 0 || *f->h_count == 0))
+      std::fprintf(stderr, "[glm %.3fs] %s pcg it %lld active rhs %d\n", now_s(),
+                   sizeof(T) == 8 ? "fp64" : "fp32", (long long)it, *f->h_count);
+    if (*f->h_count == 0) break;
+    if (chunk) {
+      GLM_CHECK(hipGraphLaunch(chunk, s));
+      f->launches += 5 * kPollEvery;
+    } else {
+      // iterations past the bound are stopped by the per-rhs limits on the device
+      const int64_t nit = std::min<int64_t>(kPollEvery, maxit_all + 1 - it);
+      for (int64_t j = 0; j < nit; ++j)
+        if (int rc = iteration(s)) return rc;
+    }
   }
   // termination: beta = X*^T (y - Sigma w) for every solved rhs
   GLM_CHECK(launch_activate(f->d_inst(), p.B, f->d_st(), f->d_active(), s));
@@ -1111,7 +1191,8 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
   double* W = f->at<double>(r.o_W);
   double* T = f->at<double>(r.o_T);
   double* Q1 = f->at<double>(r.o_Q1);
-  double* Zp = f->at<double>(r.o_Zp);
+  double* Tleaf = f->at<double>(r.o_Tleaf);
+  double* Stk = f->at<double>(r.o_Stk);
   // the descriptor vectors live in the handle, so the copies may stay in flight
   hipError_t e = hipMemcpyAsync(f->ws + r.o_desc, r.d_dev.data(),
                                 sizeof(RedDesc) * r.d_dev.size(), hipMemcpyHostToDevice, stream);
@@ -1122,16 +1203,15 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
     e = hipMemcpyAsync(f->ws + r.o_t2, r.t2.data(), sizeof(GemmTile) * r.t2.size(),
                        hipMemcpyHostToDevice, stream);
   if (!e) e = hipMemcpyAsync(W, X, 8 * r.sumMn, hipMemcpyDeviceToDevice, stream);
-  for (int p = 0; p < r.maxpan && !e; ++p) {
-    e = launch_red_panel(dd, r.B, p, W, f->at<double>(r.o_tau), T, stream);
-    if (!e)
-      e = launch_red_apply(dd, r.B, p, W, T, W, Zp, 0, 1, r.maxn - p * RED_PANEL,
-                           r.maxM - p * RED_PANEL, stream);
-  }
+  for (int p = 0; p < r.maxpan && !e; ++p)
+    // trailing columns: n - c0 - w, with w < 32 where kr = min(M, n) ends the
+    // panel early, so the bound is n - c0
+    e = launch_red_panel(dd, r.B, p, r.maxseg, r.maxn - p * RED_PANEL, W, Tleaf, Stk,
+                         f->at<double>(r.o_tau), T, stream);
   if (!e) e = launch_red_qinit(dd, r.B, Q1, stream);
   for (int p = r.maxpan - 1; p >= 0 && !e; --p)
-    e = launch_red_apply(dd, r.B, p, W, T, Q1, Zp, 1, 0, r.maxMr - p * RED_PANEL,
-                         r.maxM - p * RED_PANEL, stream);
+    e = launch_red_q1_panel(dd, r.B, p, r.maxseg, r.maxMr - p * RED_PANEL, W, Tleaf, Stk, T, Q1,
+                            stream);
   if (!e) e = launch_red_extract(dd, r.B, W, f->at<double>(r.o_Xr), stream);
   if (e != hipSuccess) {
     delete f;
@@ -1295,6 +1375,7 @@ int factor_entry(const glm_shape* shape, glm_precision prec, const double* X,
       return GLM_EHIP;
     }
     f->h_count_pinned = true;
+    f->use_graphs = graphs_on();
   } else {
     f->h_count = f->h_count_host;   // pageable: the poll copy completes at the stream sync
   }
@@ -1478,6 +1559,8 @@ void glm_factor_destroy(glm_factor* f) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
   }
+  for (auto& ge : f->graphs) (void)hipGraphExecDestroy(ge.exec);
+  if (f->cap_stream) (void)hipStreamDestroy(f->cap_stream);
   if (f->h_count_pinned) (void)hipHostFree(f->h_count);
   delete f;
 }

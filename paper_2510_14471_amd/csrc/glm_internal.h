@@ -96,6 +96,10 @@ struct RedDesc {
   int kr;          // reflectors: min(M, n)
   int rhs0;        // first (instance, rhs) index
   int inst;        // batch index of the instance
+  int nseg0;       // row segments of the first panel's TSQR (ceil(M / 256))
+  int pad;
+  int64_t leaf_off;  // T factors of the TSQR leaves (panels x nseg0 x 32 x 32)
+  int64_t stk_off;   // stacked R factors / tree reflectors (panels x nseg0 x 32 x 32)
   int64_t w_off;   // W copy: reflectors and R (M x n, row-major); also X and dX
   int64_t q1_off;  // Q1 = Q [I; 0] (M x Mr)
   int64_t b_off;   // beta-like (n x K)
@@ -105,9 +109,8 @@ struct RedDesc {
   int64_t tau_off; // reflector scalars (n)
   int64_t t_off;   // block-reflector factors T (panels x 32 x 32)
   int64_t om_off;  // Omega (G x G)
-  int64_t zp_off;  // partial products V^T C of the row segments
-                   // (ceil(M / RED_SEG) x max(32 (n + 1), G G)), also the
-                   // per-segment dOmega partials of the reverse mode
+  int64_t zp_off;  // per-segment dOmega partials of the reverse mode
+                   // (ceil(M / RED_SEG) x G G)
 };
 
 // One 64 x 64 output tile of a batched product with Q1 (inst < 0: padding).
@@ -115,7 +118,8 @@ struct GemmTile {
   int inst, i0, j0, pad;
 };
 constexpr int RED_PANEL = 32;    // columns per Householder panel
-constexpr int RED_SEG = 512;     // rows per workgroup of a block-reflector apply
+constexpr int RED_SEG = 512;     // rows per workgroup of the reverse-mode dOmega partials
+constexpr int RED_LEAF = 256;    // rows per TSQR leaf segment
 
 // Arguments of the two projection-pass kernels (host side).
 template <typename T>
@@ -226,11 +230,12 @@ hipError_t launch_select_inner(const InstDesc* insts, int B, RhsState* st, const
                                int* inst_active, int want, hipStream_t s);
 hipError_t launch_update_c(const InstDesc* insts, int B, const RhsState* st,
                            const double* dwc, double* wc64, hipStream_t s);
-hipError_t launch_red_panel(const RedDesc* d, int B, int panel, double* W, double* tau,
-                           double* T, hipStream_t s);
-hipError_t launch_red_apply(const RedDesc* d, int B, int panel, const double* W,
-                           const double* T, double* C, double* Zp, int target_q1, int trans,
-                           int maxcols, int maxrows, hipStream_t s);
+hipError_t launch_red_panel(const RedDesc* d, int B, int panel, int maxseg, int maxcols,
+                           double* W, double* Tleaf, double* Stk, double* tau, double* T,
+                           hipStream_t s);
+hipError_t launch_red_q1_panel(const RedDesc* d, int B, int panel, int maxseg, int maxcols,
+                              const double* W, const double* Tleaf, const double* Stk,
+                              const double* T, double* Q1, hipStream_t s);
 hipError_t launch_red_qinit(const RedDesc* d, int B, double* Q1, hipStream_t s);
 hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, double* Xr,
                              hipStream_t s);

@@ -233,9 +233,9 @@ k_qr32(const QRJob* __restrict__ jobs, double* __restrict__ A, double* __restric
 
   __shared__ Qr32Shared<QNT> sh;
   __shared__ double fro2;
+  __shared__ double wk[32];   // the Q formation's v^T a_c of the next reflector
   double (*red)[QW] = sh.red;
   double* dsum = sh.dsum;
-  double* wk = sh.wk;
   const double* tau_s = sh.tau_s;
 
   const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;

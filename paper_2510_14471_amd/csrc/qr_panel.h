@@ -64,8 +64,7 @@ template <int NT>
 struct Qr32Shared {
   double red[32][NT / 64];
   double dsum[32];
-  double pivrow[32];
-  double wk[32];
+  double pivrow[2][32];   // the pivot rows of consecutive reflectors, alternating
   double tau_s[32];
   double par[3];
 };
@@ -78,8 +77,6 @@ __device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
                 "whole waves; rows per sweep step a power of two");
   double (*red)[NT / 64] = sh.red;
   double* dsum = sh.dsum;
-  double* pivrow = sh.pivrow;
-  double* wk = sh.wk;
   double* tau_s = sh.tau_s;
   double* par = sh.par;
   const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
@@ -89,7 +86,10 @@ __device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
     const double beta_j = (p > 0) ? par[0] : 0.0;
     const double tau_j = (p > 0) ? par[1] : 0.0;
     const double scale_j = (p > 0) ? par[2] : 0.0;
-    const double wkc = (p > 0 && c > j && colok) ? wk[c] : 0.0;
+    // v^T a_c of reflector j (v = [1; x scale]) from its pivot row and dot
+    // products; each lane forms its own column's
+    const double wkc =
+        (p > 0 && c > j && colok) ? sh.pivrow[j & 1][c] + scale_j * dsum[c] : 0.0;
     const int lo = (j > 0) ? j : 0;
     double dot = 0.0;
     // the sweep starts at a multiple of SLOTS * U, so that a row is
@@ -114,7 +114,7 @@ __device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
           if (rok && colok && c >= j) a0[(int64_t)t * ld + c] = x;
         }
         if (p < cols) {
-          if (rok && t == p && colok && c >= p) pivrow[c] = x;
+          if (rok && t == p && colok && c >= p) sh.pivrow[p & 1][c] = x;
           // dot products of the subcolumn below the pivot with every column
           const double ap = shfl_col(x, p);
           if (rok && t > p && c >= p) dot += ap * x;
@@ -125,7 +125,7 @@ __device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
     __syncthreads();  // pivrow visible, all rows written
     col_sum<NT>(dot, p, cols, red, dsum);
     if (tid == 0) {
-      const double alpha = pivrow[p];
+      const double alpha = sh.pivrow[p & 1][p];
       const double xnorm2 = dsum[p];            // squared norm below the pivot
       const double nrm2 = alpha * alpha + xnorm2;
       double beta, tau, scale;
@@ -143,8 +143,6 @@ __device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
       par[1] = tau;
       par[2] = scale;
       tau_s[p] = tau;
-      for (int k = p + 1; k < cols; ++k)
-        wk[k] = pivrow[k] + scale * dsum[k];    // v^T a_k with v = [1; x * scale]
     }
     __syncthreads();
   }

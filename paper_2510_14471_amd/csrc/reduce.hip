@@ -4,12 +4,13 @@
 // rows t >= n carry no information on beta, so the GLS of the first
 // Mr = min(M, n + 1) rotated rows is the GLS of the full model.
 //
-// Factorization (once per W): Householder panels of RED_PANEL columns in
-// compact WY form, B_p = I - V_p T_p V_p^T (T_p upper triangular), applied to
-// the trailing columns of W; then the explicit first Mr columns of
-// Q = B_0 B_1 ..., Q1 = Q [I; 0] (M x Mr), accumulated backwards.
-//   k_red_panel       factor panel p in place, store tau and T_p
-//   k_red_apply_z/_c  C <- B_p^T C (trailing columns of W) or C <- B_p C (Q1)
+// Factorization (once per W): panels of RED_PANEL columns, each factored
+// TSQR-wise (independent row segments, then the stack of their R factors)
+// and applied to the trailing columns of W; then the explicit first Mr
+// columns of Q = Q_0 Q_1 ..., Q1 = Q [I; 0] (M x Mr), accumulated backwards.
+//   k_tsqr_leaf, k_tsqr_tree       factor panel p (below)
+//   k_leaf_apply, k_tree_apply     C <- Q_p^T C (trailing columns of W) or
+//                                  C <- Q_p C (Q1)
 //   k_red_qinit       Q1 <- [I; 0]
 //   k_red_extract     reduced regressors (the rows of R)
 // Solve (per right-hand side block Y, M x G K):
@@ -28,6 +29,7 @@
 #include "glm_internal.h"
 #include "qr_panel.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace glm {
@@ -35,7 +37,6 @@ namespace glm {
 namespace {
 
 constexpr int RP = RED_PANEL;
-constexpr int RCH = 128;  // rows of V staged in LDS per chunk
 
 // V[r][j] of panel rows r (relative to the panel's first row): the unit
 // diagonal and zeros above it are implicit in the stored factorization.
@@ -46,36 +47,183 @@ __device__ __forceinline__ double vpanel(const double* __restrict__ a0, int ld, 
   return r > j ? a0[(int64_t)r * ld + j] : 0.0;
 }
 
-// The panel kernel runs RPNT threads per instance: the panel passes are
-// sequential over the rows, so the rows in flight per instance set its time.
-constexpr int RPNT = 1024;
-constexpr int RPU = 16;             // rows in flight per lane in the panel passes
-constexpr int RPW = RPNT / 64;      // waves per panel workgroup
+// Panel factorization, TSQR form.  Panel p holds the columns [c0, c0 + w),
+// c0 = 32 p, of the rows [c0, M).  Those rows are cut into segments of TS
+// rows; every segment is factored on its own (leaf: A_s = Q_s [R_s; 0]) and
+// the R_s, stacked 32 rows apart, are factored once more (tree:
+// [R_0; R_1; ...] = Q_t [R; 0]).  The panel's orthogonal factor is
+// Q_p = diag(Q_s) Q_t, with Q_t acting on the first rows of the segments, and
+// R goes to the panel's first rows.  Each Q_s and Q_t is kept in compact WY
+// form, I - V T V^T (T upper triangular): the leaves' V in place in W, the
+// tree's V in the stack buffer.
+//   k_tsqr_leaf        factor a segment in registers; V_s, T_s; R_s to the stack
+//   k_tsqr_tree        factor the stack in place; T_t; R into W
+//   k_leaf_apply       C_s <- (I - V_s op(T_s) V_s^T) C_s, one pass over C
+//   k_tree_apply       the same with Q_t on the segments' first rows
+constexpr int TS = RED_LEAF;      // rows per leaf segment
+constexpr int TSJ = TS / 8;       // rows per thread in the leaf kernels (8 row slots)
 
-__global__ void __launch_bounds__(RPNT)
-k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W,
-            double* __restrict__ tau, double* __restrict__ T) {
+// T of a block reflector (forward, columnwise): T[j][j] = tau_j,
+// T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j] with S = V^T V.  Column j needs the
+// columns before it; within a column thread i forms entry i.  Called by every
+// thread of the workgroup (NT >= 32).
+template <int NT>
+__device__ void form_t(const double (*S)[RP + 1], const double* tau, int w, double (*Tl)[RP]) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < RP * RP; e += NT) Tl[e / RP][e % RP] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    if (tid < j) {
+      double s = 0.0;
+      for (int k = tid; k < j; ++k) s += Tl[tid][k] * S[k][j];
+      Tl[tid][j] = -tau[j] * s;
+    } else if (tid == j) {
+      Tl[j][j] = tau[j];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W,
+            double* __restrict__ Tleaf, double* __restrict__ Stk) {
   const RedDesc d = descs[blockIdx.x];
   const int c0 = panel * RP;
   if (c0 >= d.kr) return;
-  const int w = min(RP, d.kr - c0), rows = d.M - c0, ld = d.n;
-  double* a0 = W + d.w_off + (int64_t)c0 * ld + c0;
-  __shared__ Qr32Shared<RPNT> sh;
+  const int w = min(RP, d.kr - c0), rows_all = d.M - c0, sg = blockIdx.y, r0 = sg * TS;
+  if (r0 >= rows_all) return;
+  const int rs = min(TS, rows_all - r0), ws = min(rs, w), ld = d.n;
+  double* a0 = W + d.w_off + (int64_t)(c0 + r0) * ld + c0;
+  const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
+  const bool colok = c < w;
+  __shared__ double red[32][4];
+  __shared__ double dsum[32], pivrow[32], tau_s[32], par[3];
   __shared__ double S[RP][RP + 1];
   __shared__ double part[4][RP][RP];
-  qr32_factor<RPNT, RPU>(a0, rows, w, ld, sh);
-  const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
-  if (tid < w) tau[d.tau_off + c0 + tid] = sh.tau_s[tid];
-  // S = V^T V: lane c accumulates S[i][c] for every i over its rows
+  double a[TSJ];
+#pragma unroll
+  for (int j = 0; j < TSJ; ++j) {
+    const int r = slot + 8 * j;
+    a[j] = (r < rs && colok) ? a0[(int64_t)r * ld + c] : 0.0;
+  }
+  if (tid < 32) tau_s[tid] = 0.0;
+  // Householder in registers, the arithmetic of qr32_factor (reflector p:
+  // v = [1; x scale], H = I - tau v v^T, a_k -= tau v (pivrow_k + scale dsum_k))
+  for (int p = 0; p < ws; ++p) {
+    double dot = 0.0;
+#pragma unroll
+    for (int j = 0; j < TSJ; ++j) {
+      const int r = slot + 8 * j;
+      const double ap = shfl_col(a[j], p);
+      if (r == p && colok) pivrow[c] = a[j];
+      if (r > p && r < rs && c >= p) dot += ap * a[j];
+    }
+    col_sum<256>(dot, p, w, red, dsum);
+    if (tid == 0) {
+      const double alpha = pivrow[p];
+      const double xnorm2 = dsum[p];
+      double beta, tau, scale;
+      if (!(xnorm2 > kQrTinyNorm2)) {
+        beta = alpha;
+        tau = 0.0;
+        scale = 0.0;
+      } else {
+        const double nrm = sqrt(alpha * alpha + xnorm2);
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      par[0] = beta;
+      par[1] = tau;
+      par[2] = scale;
+      tau_s[p] = tau;
+    }
+    __syncthreads();
+    const double beta = par[0], tau = par[1], scale = par[2];
+    const double wkc = (c > p && colok) ? pivrow[c] + scale * dsum[c] : 0.0;
+#pragma unroll
+    for (int j = 0; j < TSJ; ++j) {
+      const int r = slot + 8 * j;
+      const double ap = shfl_col(a[j], p);
+      if (r >= p && r < rs) {
+        const double vv = (r > p) ? ap * scale : 1.0;
+        if (c > p) a[j] -= tau * vv * wkc;
+        if (c == p) a[j] = (r == p) ? beta : vv;
+      }
+    }
+    __syncthreads();   // pivrow, par and wk are rewritten by the next reflector
+  }
+  // reflectors below the diagonal, R_s on and above it
+#pragma unroll
+  for (int j = 0; j < TSJ; ++j) {
+    const int r = slot + 8 * j;
+    if (r < rs && colok) a0[(int64_t)r * ld + c] = a[j];
+  }
+  // R_s into the stack (32 rows per segment; rows at or past ws and the
+  // entries below the diagonal are zero)
+  double* stk = Stk + d.stk_off + ((int64_t)panel * d.nseg0 + sg) * RP * RP;
+#pragma unroll
+  for (int j = 0; j < TSJ; ++j) {
+    const int r = slot + 8 * j;
+    if (r < RP) stk[r * RP + c] = (r < ws && colok && c >= r) ? a[j] : 0.0;
+  }
+  // S = V^T V (V with the unit diagonal, ws columns)
   double acc[RP];
 #pragma unroll
   for (int i = 0; i < RP; ++i) acc[i] = 0.0;
-  // rows r0 + slot + (RPNT / 32) q: the same half-wave that factored them
+#pragma unroll
+  for (int j = 0; j < TSJ; ++j) {
+    const int r = slot + 8 * j;
+    const double v = (c < ws && r < rs) ? (r > c ? a[j] : (r == c ? 1.0 : 0.0)) : 0.0;
+#pragma unroll
+    for (int i = 0; i < RP; ++i) acc[i] += shfl_col(v, i) * v;
+  }
+#pragma unroll
+  for (int i = 0; i < RP; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
+  const int wave = tid >> 6;
+  if ((tid & 63) < 32)
+#pragma unroll
+    for (int i = 0; i < RP; ++i) part[wave][i][c] = acc[i];
+  __syncthreads();
+  for (int e = tid; e < RP * RP; e += 256) {
+    const int i = e / RP, jj = e % RP;
+    S[i][jj] = part[0][i][jj] + part[1][i][jj] + part[2][i][jj] + part[3][i][jj];
+  }
+  __syncthreads();
+  double (*Tl)[RP] = part[0];
+  form_t<256>(S, tau_s, ws, Tl);
+  double* Tp = Tleaf + d.leaf_off + ((int64_t)panel * d.nseg0 + sg) * RP * RP;
+  for (int e = tid; e < RP * RP; e += 256) Tp[e] = Tl[e / RP][e % RP];
+}
+
+// The tree: the stack (nseg x 32 rows, ld 32) factored in place by one
+// workgroup; T_t to the panel's T slot, R into W's first panel rows.
+constexpr int RPNT = 1024;
+constexpr int RPU = 16;             // rows in flight per lane in the tree passes
+constexpr int RPW = RPNT / 64;      // waves per tree workgroup
+
+__global__ void __launch_bounds__(RPNT)
+k_tsqr_tree(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W,
+            double* __restrict__ Stk, double* __restrict__ tau, double* __restrict__ T) {
+  const RedDesc d = descs[blockIdx.x];
+  const int c0 = panel * RP;
+  if (c0 >= d.kr) return;
+  const int w = min(RP, d.kr - c0), nseg = (d.M - c0 + TS - 1) / TS, rows = nseg * RP;
+  double* a0 = Stk + d.stk_off + (int64_t)panel * d.nseg0 * RP * RP;
+  __shared__ Qr32Shared<RPNT> sh;
+  __shared__ double S[RP][RP + 1];
+  __shared__ double part[4][RP][RP];
+  qr32_factor<RPNT, RPU>(a0, rows, w, RP, sh);
+  const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
+  if (tid < w) tau[d.tau_off + c0 + tid] = sh.tau_s[tid];
+  double acc[RP];
+#pragma unroll
+  for (int i = 0; i < RP; ++i) acc[i] = 0.0;
   constexpr int SU = 4;
-  for (int r0 = 0; r0 < rows; r0 += (RPNT / 32) * SU) {
+  for (int q0 = 0; q0 < rows; q0 += (RPNT / 32) * SU) {
     double v[SU];
 #pragma unroll
-    for (int q = 0; q < SU; ++q) v[q] = vpanel(a0, ld, r0 + slot + (RPNT / 32) * q, c, rows, w);
+    for (int q = 0; q < SU; ++q) v[q] = vpanel(a0, RP, q0 + slot + (RPNT / 32) * q, c, rows, w);
 #pragma unroll
     for (int q = 0; q < SU; ++q)
 #pragma unroll
@@ -83,7 +231,6 @@ k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
   }
 #pragma unroll
   for (int i = 0; i < RP; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
-  // wave partials summed in four slots, four waves at a time in wave order
   const int wave = tid >> 6;
   for (int g = 0; g < RPW / 4; ++g) {
     if (wave / 4 == g && (tid & 63) < 32)
@@ -96,183 +243,234 @@ k_red_panel(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
   }
   for (int e = tid; e < RP * RP; e += RPNT) {
     const int i = e / RP, j = e % RP;
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) s += part[q][i][j];
-    S[i][j] = s;
+    S[i][j] = part[0][i][j] + part[1][i][j] + part[2][i][j] + part[3][i][j];
   }
   __syncthreads();
-  // T (forward, columnwise): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j];
-  // built in LDS (the partial sums are no longer needed) by one thread
   double (*Tl)[RP] = part[0];
-  for (int e = tid; e < RP * RP; e += RPNT) Tl[e / RP][e % RP] = 0.0;
-  __syncthreads();
-  if (tid == 0)
-    for (int j = 0; j < w; ++j) {
-      const double tj = sh.tau_s[j];
-      for (int i = 0; i < j; ++i) {
-        double s = 0.0;
-        for (int k = i; k < j; ++k) s += Tl[i][k] * S[k][j];
-        Tl[i][j] = -tj * s;
-      }
-      Tl[j][j] = tj;
-    }
-  __syncthreads();
+  form_t<RPNT>(S, sh.tau_s, w, Tl);
   double* Tp = T + d.t_off + (int64_t)panel * RP * RP;
   for (int e = tid; e < RP * RP; e += RPNT) Tp[e] = Tl[e / RP][e % RP];
+  // the panel's R (upper triangle of the first w rows) into W
+  for (int e = tid; e < w * w; e += RPNT) {
+    const int i = e / w, j = e % w;
+    if (j >= i) W[d.w_off + (int64_t)(c0 + i) * d.n + c0 + j] = a0[i * RP + j];
+  }
 }
 
-// C <- (I - V op(T) V^T) C on rows [c0, M) of one instance, op(T) = T^T when
-// trans (B_p^T) else T (B_p).  Target: the trailing columns of W (TGT_W) or
-// the columns c0.. of Q1 (TGT_Q1).  The rows are cut into segments of
-// RED_SEG, so that a tall instance spreads over as many workgroups as a short
-// one has rows to spare; workgroup (instance, chunk of QNT columns, segment),
-// lane per column:
-//   k_red_apply_z   partial z_s = V_s^T c_s of the segment
-//   k_red_apply_c   z = sum of the partials (fixed order), z' = op(T) z,
-//                   c_s -= V_s z'
-// V is staged in LDS RCH rows at a time, unpadded: every lane reads the same
-// V entry (a broadcast), so rows 16-byte aligned give two entries per read;
-// RU rows of c are loaded before they are used.
-constexpr int RU = 32;
-static_assert(RED_SEG % RCH == 0 && RCH % RU == 0, "segment, chunk and batch sizes nest");
+// Vs[r][j] = V[h0 + r][j] for r < TS (vpanel rows h0.. of a panel block of
+// `rows` rows and w reflector columns at a0, row stride ld), 256 threads with
+// eight loads in flight each
+__device__ __forceinline__ void stage_vpanel(double (*Vs)[RP], const double* __restrict__ a0,
+                                             int ld, int h0, int rows, int w) {
+  const int tid = threadIdx.x;
+  for (int b = 0; b < TS * RP; b += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = b + q * 256 + tid, r = h0 + e / RP, j = e % RP;
+      v[q] = (j < w && r < rows && r > j) ? a0[(int64_t)r * ld + j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = b + q * 256 + tid, r = h0 + e / RP, j = e % RP;
+      Vs[e / RP][j] = (j < w && r < rows && r == j) ? 1.0 : v[q];
+    }
+  }
+}
+
+// Target of the applies: the trailing columns of W (TGT_W, op(T) = T^T:
+// Q_p^T) or the columns c0.. of Q1 (TGT_Q1, op(T) = T: Q_p).
 enum : int { TGT_W = 1, TGT_Q1 = 2 };
 
 struct ApplyTarget {
-  const double* a0;  // panel block of the reflectors (row c0, column c0)
-  double* cb;        // row c0 of the target
-  int w, rows, ncols, ld, seg_rows, r_seg;
+  double* cb;   // row c0 of the target, first column
+  int ncols, ld;
 };
 
-// the apply's target for this workgroup, or false when it has nothing to do
 template <int TGT>
-__device__ __forceinline__ bool apply_target(const RedDesc& d, int panel, const double* W,
-                                             double* C, ApplyTarget& a) {
-  const int c0 = panel * RP;
-  if (c0 >= d.kr) return false;
-  a.w = min(RP, d.kr - c0);
-  a.rows = d.M - c0;
-  a.a0 = W + d.w_off + (int64_t)c0 * d.n + c0;
+__device__ __forceinline__ ApplyTarget apply_target(const RedDesc& d, int c0, int w, double* C) {
+  ApplyTarget a;
   if (TGT == TGT_W) {
-    a.ncols = d.n - c0 - a.w;
+    a.ncols = d.n - c0 - w;
     a.ld = d.n;
-    a.cb = C + d.w_off + (int64_t)c0 * d.n + c0 + a.w;
+    a.cb = C + d.w_off + (int64_t)c0 * d.n + c0 + w;
   } else {
     a.ncols = d.Mr - c0;
     a.ld = d.Mr;
     a.cb = C + d.q1_off + (int64_t)c0 * d.Mr + c0;
   }
-  if ((int)blockIdx.y * QNT >= a.ncols) return false;
-  a.r_seg = blockIdx.z * RED_SEG;
-  if (a.r_seg >= a.rows) return false;
-  a.seg_rows = min(RED_SEG, a.rows - a.r_seg);
-  return true;
+  return a;
 }
 
-__device__ __forceinline__ void stage_v(double (*Vs)[RP], const ApplyTarget& a, int ldw,
-                                        int r0) {
-  for (int e = threadIdx.x; e < RCH * RP; e += QNT) {
-    const int r = e / RP, j = e % RP;
-    Vs[r][j] = vpanel(a.a0, ldw, r0 + r, j, a.rows, a.w);
-  }
-}
-
+// 32 target columns of one segment: thread (row slot, column) holds the
+// column's TSJ rows of the segment in registers; Z = V^T C reduced over the
+// slots, Z' = op(T) Z, C -= V Z', one read and one write of C.  V is staged
+// twice, sharing its LDS with the reduction of Z, so that two workgroups fit
+// a CU (keeping V resident for several column chunks, at one workgroup per
+// CU, was slower).
 template <int TGT>
-__global__ void __launch_bounds__(QNT)
-k_red_apply_z(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
-              double* __restrict__ C, double* __restrict__ Zp) {
+__global__ void __launch_bounds__(256, 2)
+k_leaf_apply(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
+             const double* __restrict__ Tleaf, double* __restrict__ C) {
   const RedDesc d = descs[blockIdx.x];
-  ApplyTarget a;
-  if (!apply_target<TGT>(d, panel, W, C, a)) return;
-  __shared__ __align__(16) double Vs[RCH][RP];
-  const int col = blockIdx.y * QNT + threadIdx.x;
+  const int c0 = panel * RP;
+  if (c0 >= d.kr) return;
+  const int w = min(RP, d.kr - c0), rows_all = d.M - c0, sg = blockIdx.z, r0 = sg * TS;
+  if (r0 >= rows_all) return;
+  const ApplyTarget a = apply_target<TGT>(d, c0, w, C);
+  const int col0 = blockIdx.y * 32;
+  if (col0 >= a.ncols) return;
+  const int rs = min(TS, rows_all - r0), ws = min(rs, w);
+  const int tid = threadIdx.x, cl = tid & 31, slot = tid >> 5, col = col0 + cl;
   const bool ok = col < a.ncols;
-  const double* cc = a.cb + col;
-  double z[RP];
-#pragma unroll
-  for (int j = 0; j < RP; ++j) z[j] = 0.0;
-  for (int r0 = a.r_seg; r0 < a.r_seg + a.seg_rows; r0 += RCH) {
-    __syncthreads();
-    stage_v(Vs, a, d.n, r0);
-    __syncthreads();
-    const int nr = min(RCH, a.r_seg + a.seg_rows - r0);
-    for (int r = 0; r < nr; r += RU) {
-      double x[RU];
-#pragma unroll
-      for (int q = 0; q < RU; ++q)
-        x[q] = (ok && r + q < nr) ? cc[(int64_t)(r0 + r + q) * a.ld] : 0.0;
-#pragma unroll
-      for (int q = 0; q < RU; ++q)
-#pragma unroll
-        for (int j = 0; j < RP; ++j) z[j] += Vs[r + q][j] * x[q];
-    }
-  }
-  if (ok) {
-    double* zp = Zp + d.zp_off + (int64_t)blockIdx.z * RP * a.ncols + col;
-#pragma unroll
-    for (int j = 0; j < RP; ++j) zp[(int64_t)j * a.ncols] = z[j];
-  }
-}
-
-template <int TGT>
-__global__ void __launch_bounds__(QNT)
-k_red_apply_c(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
-              const double* __restrict__ T, double* __restrict__ C,
-              const double* __restrict__ Zp, int trans) {
-  const RedDesc d = descs[blockIdx.x];
-  ApplyTarget a;
-  if (!apply_target<TGT>(d, panel, W, C, a)) return;
+  __shared__ __align__(16) double smem[TS * RP];
   __shared__ double Ts[RP][RP + 1];
-  __shared__ __align__(16) double Vs[RCH][RP];
-  const int tid = threadIdx.x;
+  double (*Vs)[RP] = reinterpret_cast<double (*)[RP]>(smem);
+  double (*red)[RP][32] = reinterpret_cast<double (*)[RP][32]>(smem);
+  double (*Zs)[33] = reinterpret_cast<double (*)[33]>(smem + 4 * RP * 32);
+  double (*Z2s)[33] = reinterpret_cast<double (*)[33]>(smem + 4 * RP * 32 + RP * 33);
+  const double* v0 = W + d.w_off + (int64_t)(c0 + r0) * d.n + c0;
+  stage_vpanel(Vs, v0, d.n, 0, rs, ws);
   {
-    const double* Tp = T + d.t_off + (int64_t)panel * RP * RP;
-    for (int e = tid; e < RP * RP; e += QNT) {
-      const int i = e / RP, j = e % RP;
-      Ts[i][j] = trans ? Tp[j * RP + i] : Tp[i * RP + j];
+    const double* Tp = Tleaf + d.leaf_off + ((int64_t)panel * d.nseg0 + sg) * RP * RP;
+    for (int e = tid; e < RP * RP; e += 256) {
+      const int i = e / RP, jj = e % RP;
+      Ts[i][jj] = (TGT == TGT_W) ? Tp[jj * RP + i] : Tp[i * RP + jj];
     }
   }
-  const int col = blockIdx.y * QNT + tid;
-  const bool ok = col < a.ncols;
-  double* cc = a.cb + col;
+  double* cc = a.cb + (int64_t)r0 * a.ld + col;
+  double x[TSJ];
+#pragma unroll
+  for (int j = 0; j < TSJ; ++j) {
+    const int r = slot + 8 * j;
+    x[j] = (ok && r < rs) ? cc[(int64_t)r * a.ld] : 0.0;
+  }
+  __syncthreads();
   double z[RP];
 #pragma unroll
-  for (int j = 0; j < RP; ++j) z[j] = 0.0;
-  if (ok) {
-    const int nseg = (a.rows + RED_SEG - 1) / RED_SEG;
-    const double* zp = Zp + d.zp_off + col;
-    for (int s = 0; s < nseg; ++s)
+  for (int i = 0; i < RP; ++i) z[i] = 0.0;
 #pragma unroll
-      for (int j = 0; j < RP; ++j) z[j] += zp[((int64_t)s * RP + j) * a.ncols];
+  for (int j = 0; j < TSJ; ++j) {
+    const double* vr = &Vs[slot + 8 * j][0];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) z[i] += vr[i] * x[j];
   }
-  __syncthreads();  // Ts
-  double zz[RP];
+#pragma unroll
+  for (int i = 0; i < RP; ++i) z[i] += __shfl_xor(z[i], 32, 64);
+  const int wave = tid >> 6;
+  __syncthreads();   // every lane is done with Vs
+  if ((tid & 63) < 32)
+#pragma unroll
+    for (int i = 0; i < RP; ++i) red[wave][i][cl] = z[i];
+  __syncthreads();
+  for (int i = slot * 4; i < slot * 4 + 4; ++i)
+    Zs[i][cl] = red[0][i][cl] + red[1][i][cl] + red[2][i][cl] + red[3][i][cl];
+  __syncthreads();
+  for (int i = slot * 4; i < slot * 4 + 4; ++i) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < RP; ++k) s2 += Ts[i][k] * Zs[k][cl];
+    Z2s[i][cl] = s2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RP; ++i) z[i] = Z2s[i][cl];
+  __syncthreads();   // every lane has its Z' column
+  stage_vpanel(Vs, v0, d.n, 0, rs, ws);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < TSJ; ++j) {
+    const int r = slot + 8 * j;
+    const double* vr = &Vs[r][0];
+    double v = x[j];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) v -= vr[i] * z[i];
+    if (ok && r < rs) cc[(int64_t)r * a.ld] = v;
+  }
+}
+
+// Q_t on the segments' first rows: stack row h = 32 s + i is row 256 s + i of
+// the panel (i < ws_s); V_t staged in LDS TS rows at a time, two passes over
+// those target rows (Z = V_t^T C, then C -= V_t op(T_t) Z).
+template <int TGT>
+__global__ void __launch_bounds__(256, 2)
+k_tree_apply(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ Stk,
+             const double* __restrict__ T, double* __restrict__ C) {
+  const RedDesc d = descs[blockIdx.x];
+  const int c0 = panel * RP;
+  if (c0 >= d.kr) return;
+  const int w = min(RP, d.kr - c0), rows_all = d.M - c0;
+  const int nseg = (rows_all + TS - 1) / TS, H = nseg * RP;
+  const ApplyTarget a = apply_target<TGT>(d, c0, w, C);
+  const int col0 = blockIdx.y * 32;
+  if (col0 >= a.ncols) return;
+  const int tid = threadIdx.x, cl = tid & 31, slot = tid >> 5, col = col0 + cl;
+  const bool ok = col < a.ncols;
+  const double* v0 = Stk + d.stk_off + (int64_t)panel * d.nseg0 * RP * RP;
+  __shared__ __align__(16) double smem[TS * RP];   // V chunks, or the reduction of Z
+  __shared__ double Ts[RP][RP + 1];
+  __shared__ double Zs[RP][33];
+  double (*Vs)[RP] = reinterpret_cast<double (*)[RP]>(smem);
+  double (*red)[RP][32] = reinterpret_cast<double (*)[RP][32]>(smem);
+  for (int e = tid; e < RP * RP; e += 256) {
+    const int i = e / RP, j = e % RP;
+    const double* Tp = T + d.t_off + (int64_t)panel * RP * RP;
+    Ts[i][j] = (TGT == TGT_W) ? Tp[j * RP + i] : Tp[i * RP + j];
+  }
+  // target row of stack row h, or -1 for the zero rows of a short last segment
+  auto trow = [&](int h) -> int {
+    const int s = h / RP, i = h - s * RP;
+    const int rs = min(TS, rows_all - s * TS);
+    return i < min(rs, w) ? s * TS + i : -1;
+  };
+  double z[RP];
+#pragma unroll
+  for (int i = 0; i < RP; ++i) z[i] = 0.0;
+  for (int h0 = 0; h0 < H; h0 += TS) {
+    __syncthreads();
+    stage_vpanel(Vs, v0, RP, h0, H, w);
+    __syncthreads();
+    for (int j = 0; j < TSJ; ++j) {
+      const int h = h0 + slot + 8 * j;
+      const int tr = h < H ? trow(h) : -1;
+      const double x = (ok && tr >= 0) ? a.cb[(int64_t)tr * a.ld + col] : 0.0;
+      const double* vr = &Vs[slot + 8 * j][0];
+#pragma unroll
+      for (int i = 0; i < RP; ++i) z[i] += vr[i] * x;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RP; ++i) z[i] += __shfl_xor(z[i], 32, 64);
+  const int wave = tid >> 6;
+  __syncthreads();   // every lane is done with the last V chunk
+  if ((tid & 63) < 32)
+#pragma unroll
+    for (int i = 0; i < RP; ++i) red[wave][i][cl] = z[i];
+  __syncthreads();
+  for (int i = slot * 4; i < slot * 4 + 4; ++i)
+    Zs[i][cl] = red[0][i][cl] + red[1][i][cl] + red[2][i][cl] + red[3][i][cl];
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < RP; ++i) {
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < RP; ++j) s += Ts[i][j] * z[j];
-    zz[i] = s;
+    for (int k = 0; k < RP; ++k) s += Ts[i][k] * Zs[k][cl];
+    z[i] = s;
   }
-  for (int r0 = a.r_seg; r0 < a.r_seg + a.seg_rows; r0 += RCH) {
+  for (int h0 = 0; h0 < H; h0 += TS) {
     __syncthreads();
-    stage_v(Vs, a, d.n, r0);
+    stage_vpanel(Vs, v0, RP, h0, H, w);
     __syncthreads();
-    const int nr = min(RCH, a.r_seg + a.seg_rows - r0);
-    if (ok)
-      for (int r = 0; r < nr; r += RU) {
-        double x[RU];
+    for (int j = 0; j < TSJ; ++j) {
+      const int h = h0 + slot + 8 * j;
+      const int tr = h < H ? trow(h) : -1;
+      if (!(ok && tr >= 0)) continue;
+      const double* vr = &Vs[slot + 8 * j][0];
+      double v = a.cb[(int64_t)tr * a.ld + col];
 #pragma unroll
-        for (int q = 0; q < RU; ++q)
-          x[q] = (r + q < nr) ? cc[(int64_t)(r0 + r + q) * a.ld] : 0.0;
-#pragma unroll
-        for (int q = 0; q < RU; ++q) {
-          double v = x[q];
-#pragma unroll
-          for (int j = 0; j < RP; ++j) v -= Vs[r + q][j] * zz[j];
-          if (r + q < nr) cc[(int64_t)(r0 + r + q) * a.ld] = v;
-        }
-      }
+      for (int i = 0; i < RP; ++i) v -= vr[i] * z[i];
+      a.cb[(int64_t)tr * a.ld + col] = v;
+    }
   }
 }
 
@@ -773,29 +971,33 @@ k_red_grad_x(const RedDesc* __restrict__ descs, const InstDesc* __restrict__ sin
 
 }  // namespace
 
-hipError_t launch_red_panel(const RedDesc* d, int B, int panel, double* W, double* tau,
-                           double* T, hipStream_t s) {
-  if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_red_panel, dim3(B), dim3(RPNT), 0, s, d, panel, W, tau, T);
+hipError_t launch_red_panel(const RedDesc* d, int B, int panel, int maxseg, int maxcols,
+                           double* W, double* Tleaf, double* Stk, double* tau, double* T,
+                           hipStream_t s) {
+  if (B <= 0 || maxseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tsqr_leaf, dim3(B, maxseg), dim3(256), 0, s, d, panel, W, Tleaf, Stk);
+  if (hipError_t e = hipGetLastError()) return e;
+  if (maxcols > 0)
+    hipLaunchKernelGGL(k_leaf_apply<TGT_W>, dim3(B, (maxcols + 31) / 32, maxseg), dim3(256), 0,
+                       s, d, panel, (const double*)W, (const double*)Tleaf, W);
+  if (hipError_t e = hipGetLastError()) return e;
+  hipLaunchKernelGGL(k_tsqr_tree, dim3(B), dim3(RPNT), 0, s, d, panel, W, Stk, tau, T);
+  if (hipError_t e = hipGetLastError()) return e;
+  if (maxcols > 0)
+    hipLaunchKernelGGL(k_tree_apply<TGT_W>, dim3(B, (maxcols + 31) / 32), dim3(256), 0, s, d,
+                       panel, (const double*)Stk, (const double*)T, W);
   return hipGetLastError();
 }
 
-hipError_t launch_red_apply(const RedDesc* d, int B, int panel, const double* W,
-                           const double* T, double* C, double* Zp, int target_q1, int trans,
-                           int maxcols, int maxrows, hipStream_t s) {
-  if (B <= 0 || maxcols <= 0 || maxrows <= 0) return hipSuccess;
-  const dim3 grid(B, (maxcols + QNT - 1) / QNT, (maxrows + RED_SEG - 1) / RED_SEG);
-  if (target_q1)
-    hipLaunchKernelGGL(k_red_apply_z<TGT_Q1>, grid, dim3(QNT), 0, s, d, panel, W, C, Zp);
-  else
-    hipLaunchKernelGGL(k_red_apply_z<TGT_W>, grid, dim3(QNT), 0, s, d, panel, W, C, Zp);
+hipError_t launch_red_q1_panel(const RedDesc* d, int B, int panel, int maxseg, int maxcols,
+                              const double* W, const double* Tleaf, const double* Stk,
+                              const double* T, double* Q1, hipStream_t s) {
+  if (B <= 0 || maxseg <= 0 || maxcols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tree_apply<TGT_Q1>, dim3(B, (maxcols + 31) / 32), dim3(256), 0, s, d,
+                     panel, Stk, T, Q1);
   if (hipError_t e = hipGetLastError()) return e;
-  if (target_q1)
-    hipLaunchKernelGGL(k_red_apply_c<TGT_Q1>, grid, dim3(QNT), 0, s, d, panel, W, T, C,
-                       (const double*)Zp, trans);
-  else
-    hipLaunchKernelGGL(k_red_apply_c<TGT_W>, grid, dim3(QNT), 0, s, d, panel, W, T, C,
-                       (const double*)Zp, trans);
+  hipLaunchKernelGGL(k_leaf_apply<TGT_Q1>, dim3(B, (maxcols + 31) / 32, maxseg), dim3(256), 0,
+                     s, d, panel, W, Tleaf, Q1);
   return hipGetLastError();
 }
 
