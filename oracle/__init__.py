@@ -12,7 +12,8 @@ Contents
   grad.py     dense reference gradients of the GLS estimator (unrestricted
               and restricted)
   reduce.py   the SUR model reduction (QR of W = [X_1 ... X_G])
+  pcg_ne.py   CG on the normal equations (the paper's PCG-NE comparator)
 
 Parity status of every function is stated in its docstring.
 """
-from . import gls, pcg_aug, grad, reduce  # noqa: F401
+from . import gls, pcg_aug, pcg_ne, grad, reduce  # noqa: F401

@@ -640,3 +640,59 @@ def test_planted_mistake_scalar_norm_with_per_equation_d_is_caught():
     g1w = g - lam_wrong * ops.Pi(ops.Sigma(u))
     assert np.linalg.norm(g1) < 1e-12 * np.linalg.norm(g)
     assert np.linalg.norm(g1w) > 1e-3 * np.linalg.norm(g)
+
+
+# -- PCG-NE: CG on the normal equations (the Monte Carlo comparator) -----------
+
+def test_pcg_ne_converges_to_gls_with_monotone_a_norm_error():
+    from oracle import pcg_ne
+    for inst in _nonsingular_batch()[:3]:
+        beta, _ = gls.sur_gls(inst)
+        A, b, _ = pcg_ne.normal_system(inst, 0)
+        for precond in ("block", "none"):
+            res = pcg_ne.pcg_ne(inst, tol=1e-13, precond=precond, keep=True,
+                                max_iter=4 * inst.n)
+            assert res.status == "converged", (precond, res.status)
+            assert rel_err(res.beta, beta[:, 0]) < 1e-10
+            errs = [float((x - beta[:, 0]) @ A @ (x - beta[:, 0])) for x in res.iterates]
+            assert all(e2 <= e1 * (1 + 1e-8) + 1e-18 for e1, e2 in zip(errs, errs[1:]))
+
+
+def test_pcg_ne_block_jacobi_on_diagonal_omega_is_one_step_ols():
+    """A diagonal Omega makes the normal matrix block diagonal, which the
+    block-Jacobi preconditioner inverts exactly: one step, at blockwise OLS."""
+    from oracle import pcg_ne
+    inst = synth.small_batch(seed=5, B=1, G_rng=(3, 3), M_rng=(50, 50),
+                             n_rng=(2, 4), K_rng=(1, 1))[0]
+    inst.Omega = np.diag([0.7, 1.9, 3.1])
+    res = pcg_ne.pcg_ne(inst, tol=1e-13)
+    assert res.iterations == 1 and rel_err(res.beta, _blockwise_ols(inst)[:, 0]) < 1e-12
+
+
+def test_pcg_ne_early_iterates_are_biased_unlike_pcg_aug():
+    """Started from beta_0 = 0, the CG iterates on the normal equations are
+    shrunk toward 0 (biased), while PCG-Aug's estimate is unbiased at every
+    iteration (Theorem on the unbiasedness of the PCG-Aug iterates)."""
+    from oracle import pcg_ne
+    base = synth.small_batch(seed=73, B=1, G_rng=(3, 3), M_rng=(40, 40), n_rng=(2, 3),
+                             K_rng=(1, 1), shift=0.5)[0]
+    base.beta_true[:, 0] = 3.0 + np.arange(base.n)          # far from the start point 0
+    rng = np.random.default_rng(11)
+    L = np.linalg.cholesky(base.Omega)
+    fit = gls.fitted(base, base.beta_true)[:, :, 0]
+    R = 400
+    e_ne, e_aug = [], []
+    for _ in range(R):
+        E = rng.standard_normal((base.M, base.G)) @ L.T
+        inst = synth.SURInstance(base.n_i, base.W, base.Omega, (fit + E)[:, :, None],
+                                 base.beta_true)
+        e_ne.append(pcg_ne.pcg_ne(inst, tol=0.0, max_iter=1, precond="none").beta -
+                    base.beta_true[:, 0])
+        e_aug.append(pcg_aug.pcg_aug(inst, tol=0.0, max_iter=1, stall=10**9).z_hat -
+                     base.beta_true[:, 0])
+    for e, biased in ((np.array(e_ne), True), (np.array(e_aug), False)):
+        z = np.abs(e.mean(0)) / (e.std(0, ddof=1) / np.sqrt(R))
+        if biased:
+            assert z.max() > 10.0, z
+        else:
+            assert z.max() < 4.0, z
