@@ -252,6 +252,37 @@ int glm_gls_backward(glm_factor* f, const double* Omega,
                      double* dy, double* dOmega, double* dX,
                      int32_t* info, int32_t* iters, hipStream_t stream);
 
+/* The comparator of PCG-Aug in the study of its statistical properties
+ * (section on the statistical properties of the PCG-Aug estimator; the VAR
+ * experiments): conjugate gradients on the normal equations
+ *     (X^T Sigma^-1 X) beta = X^T Sigma^-1 y,   Sigma^-1 = Omega^-1 (x) I_M,
+ * from beta_0 = 0, in double precision on any unrestricted handle (GLM_FP64
+ * or GLM_MIXED; on a GLM_REDUCED handle on the reduced model, whose GLS
+ * estimate is the full model's).  Preconditioner: block Jacobi with the
+ * diagonal blocks w^ii X_i^T X_i = w^ii R_i^T R_i of the normal matrix
+ * ([w^ij] = Omega^-1; one pair of triangular solves per equation).  The
+ * normal matrix is never formed: each iteration applies it as X^T ((X p)
+ * Omega^-1).  Unlike PCG-Aug's, its early iterates are biased toward 0.
+ *
+ *   Omega     device, G_b x G_b per instance, symmetric positive definite
+ *             (an instance whose Omega is numerically singular -- largest
+ *             remaining pivot of a diagonally pivoted Cholesky at most
+ *             16 G eps trace(Omega) -- reports GLM_INFO_BREAKDOWN, beta = 0)
+ *   y         device, M_b x G_b x K_b per instance
+ *   tol       stop when ||b - A beta_i|| <= tol ||b||, b = X^T Sigma^-1 y
+ *   max_iter  iteration limit per (instance, rhs); <= 0 selects n_b
+ *   beta      device out, n_b x K_b per instance (the last iterate)
+ *   info      device out, int32 per (instance, rhs): GLM_INFO_CONVERGED,
+ *             GLM_INFO_NOCONV (limit reached), GLM_INFO_BREAKDOWN
+ *             (p^T A p <= 0, not finite, or Omega singular), GLM_INFO_RANK;
+ *             or NULL
+ *   iters     device out, int32 per (instance, rhs): iterations, or NULL
+ * Blocks the calling thread like glm_gls_solve.  GLM_OK, GLM_EINVAL,
+ * GLM_EHIP, or GLM_EUNSUPPORTED for a handle with restricted instances. */
+int glm_gls_solve_ne(glm_factor* f, const double* Omega, const double* y, double tol,
+                     int32_t max_iter, double* beta, int32_t* info, int32_t* iters,
+                     hipStream_t stream);
+
 /* Copies the factors out of the workspace (enqueued on `stream`):
  *   Q      device out, M_b x n_b per instance, laid out like X (may be NULL)
  *   R      device out, the R_i (n_i x n_i, row-major, upper triangular) of every

@@ -21,6 +21,7 @@ SOURCES = [
     ("proj.hip", "proj_f64.o", ["-DGLM_PROJ_T=double"]),
     ("aux.hip", "aux.o", []),
     ("reduce.hip", "reduce.o", []),
+    ("ne.hip", "ne.o", []),
     ("api.hip", "api.o", []),
 ]
 ARCH = os.environ.get("GLM_OFFLOAD_ARCH", "gfx950")

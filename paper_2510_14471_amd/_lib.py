@@ -68,6 +68,8 @@ def _load():
     lib.glm_qr_factor_static.restype = c_int
     lib.glm_gls_solve.argtypes = [P, P, P, P, c_double, c_int32, P, P, P, P, P, P]
     lib.glm_gls_solve.restype = c_int
+    lib.glm_gls_solve_ne.argtypes = [P, P, P, c_double, c_int32, P, P, P, P]
+    lib.glm_gls_solve_ne.restype = c_int
     lib.glm_gls_backward.argtypes = [P, P, P, P, P, P, c_double, c_int32, P, P, P, P, P, P]
     lib.glm_gls_backward.restype = c_int
     lib.glm_copy_factors.argtypes = [P, P, P, P, P]
@@ -91,7 +93,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["glm_validate_shape", "glm_workspace_bytes", "glm_qr_factor",
-            "glm_qr_factor_static", "glm_gls_solve",
+            "glm_qr_factor_static", "glm_gls_solve", "glm_gls_solve_ne",
             "glm_gls_backward", "glm_copy_factors", "glm_plan_passes", "glm_get_stats",
             "glm_profile_enable", "glm_profile_read", "glm_factor_destroy", "glm_strerror"]
 
@@ -168,6 +170,13 @@ def glm_gls_solve(h, Omega, y, r, tol, max_iter, beta, u, uc, info, iters, strea
     rc = _lib.glm_gls_solve(h, _dp(Omega), _dp(y), _dp(r), float(tol), int(max_iter),
                             _dp(beta), _dp(u), _dp(uc), _dp(info), _dp(iters), _stream(stream))
     _check(rc, "glm_gls_solve")
+    return rc
+
+
+def glm_gls_solve_ne(h, Omega, y, tol, max_iter, beta, info, iters, stream=None) -> int:
+    rc = _lib.glm_gls_solve_ne(h, _dp(Omega), _dp(y), float(tol), int(max_iter), _dp(beta),
+                               _dp(info), _dp(iters), _stream(stream))
+    _check(rc, "glm_gls_solve_ne")
     return rc
 
 

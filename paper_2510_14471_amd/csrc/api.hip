@@ -167,7 +167,8 @@ struct Plan {
   size_t o_Q64, o_Q32, o_R, o_Nb, o_colblk, o_inst, o_blk, o_tile, o_qrs, o_qrn, o_chunks,
       o_rinst, o_rinst_index, o_flags, o_active, o_icount, o_count, o_st, o_ost, o_alpha, o_deq,
       o_Om32, o_g, o_u, o_wf, o_yf, o_y64, o_Tpart, o_Tm, o_dpart, o_cpart, o_gc, o_uc, o_wc,
-      o_wc64, o_rho0, o_rhoc, o_lb, o_eye, o_mone, o_ypart, o_bytes;
+      o_wc64, o_rho0, o_rhoc, o_lb, o_eye, o_mone, o_ypart, o_bytes, o_ne_oinv, o_ne_a,
+      o_ne_r, o_ne_z, o_ne_p;
   size_t total = 0;
 };
 
@@ -440,6 +441,12 @@ int make_plan(const glm_shape* s, glm_precision prec_flags, Plan& p, bool allow3
   p.o_mone = take(prec == GLM_MIXED ? 8 * p.B : 0);
   p.o_ypart = take(prec == GLM_MIXED ? 8 * (size_t)p.ntiles * KMAX : 0);
   p.o_bytes = take(2 * sizeof(unsigned long long));
+  // normal-equations solver: Omega^-1 (and its work area), r, z and p
+  p.o_ne_oinv = take(8 * p.sumG2);
+  p.o_ne_a = take(8 * p.sumG2);
+  p.o_ne_r = take(8 * p.sumTK);
+  p.o_ne_z = take(8 * p.sumTK);
+  p.o_ne_p = take(8 * p.sumTK);
   p.total = o;
   return GLM_OK;
 }
@@ -1126,6 +1133,82 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
   return map_info_and_stats(f, info, iters, mixed, s);
 }
 
+// PCG-NE (CG on the normal equations, block-Jacobi preconditioner) on an
+// unreduced handle in double precision.  The products with the normal
+// matrix run on the projection passes with X in place of Q and Omega^-1 in
+// place of Omega:
+//   T = X^T (0 - w Omega^-1)   pass A, RHS form (w := X p; -b with w := y)
+//   w = X T                    pass B, EXPAND form with T := p
+int ne_driver(glm_factor* f, const double* Om, const double* y, double tol, int32_t max_iter,
+              double* beta, int32_t* info, int32_t* iters, hipStream_t s) {
+  const Plan& p = f->p;
+  if (p.sumCK > 0) return GLM_EUNSUPPORTED;
+  f->launches = 0;
+  f->stats = glm_stats{};
+  pass_stats(p, &f->stats);
+  double* Oinv = f->at<double>(p.o_ne_oinv);
+  double* w = f->at<double>(p.o_g);
+  double* Tm = f->at<double>(p.o_Tm);
+  double* rv = f->at<double>(p.o_ne_r);
+  double* zv = f->at<double>(p.o_ne_z);
+  double* pv = f->at<double>(p.o_ne_p);
+  int* icount = f->at<int>(p.o_icount);
+  GLM_CHECK(launch_state_init(f->d_inst(), p.B, f->at<int>(p.o_flags), p.nblk,
+                              f->at<int>(p.o_rinst_index), f->d_st(), f->d_active(), nullptr,
+                              s));
+  GLM_CHECK(launch_ne_oinv(f->d_inst(), p.B, Om, f->at<double>(p.o_ne_a), Oinv, f->d_st(),
+                           f->d_active(), s));
+  GLM_CHECK(launch_fill<double>(w, p.sumMGK, 0.0, s));
+  f->launches += 3;
+  auto normal_product = [&](const double* wsrc) -> int {
+    // the RHS form only reads w
+    PassLaunch<double> a =
+        pass_args<double>(f, f->X, Oinv, nullptr, const_cast<double*>(wsrc), nullptr, nullptr,
+                          false);
+    a.deq = nullptr;
+    a.w_nonzero = 1;
+    if (int rc = run_pass_a<double>(f, a, PASS_A_RHS, s)) return rc;
+    GLM_CHECK(launch_reduce_t<double>(f->d_inst(), f->d_tile(), f->d_active(),
+                                      f->at<RedChunk>(p.o_chunks), (int)p.chunks.size(),
+                                      f->at<double>(p.o_Tpart), Tm, p.cfg[1].rowpass, s));
+    ++f->launches;
+    return GLM_OK;
+  };
+  // T = -X^T Sigma^-1 y, then r = b, z, p, rho
+  if (int rc = normal_product(y)) return rc;
+  GLM_CHECK(launch_ne_start(f->d_inst(), f->d_blk(), p.B, f->at<double>(p.o_R), Oinv, Tm, beta,
+                            rv, zv, pv, f->d_st(), f->d_active(), icount, s));
+  ++f->launches;
+  int64_t maxit_all = 0;
+  for (const auto& in : p.inst)
+    maxit_all = std::max<int64_t>(maxit_all, max_iter > 0 ? max_iter : in.n);
+  for (int64_t it = 0; it < maxit_all; it += kPollEvery) {
+    GLM_CHECK(launch_count(icount, p.B, f->at<int>(p.o_count), s));
+    GLM_CHECK(hipMemcpyAsync(f->h_count, f->at<int>(p.o_count), sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    GLM_CHECK(hipStreamSynchronize(s));
+    if (log_on() && (it % (kPollEvery * 16) == 0 || *f->h_count == 0))
+      std::fprintf(stderr, "[glm %.3fs] pcg-ne it %lld active rhs %d\n", now_s(), (long long)it,
+                   *f->h_count);
+    if (*f->h_count == 0) break;
+    const int64_t nit = std::min<int64_t>(kPollEvery, maxit_all - it);
+    for (int64_t j = 0; j < nit; ++j) {
+      PassLaunch<double> a = pass_args<double>(f, f->X, Oinv, nullptr, w, nullptr, nullptr, false);
+      a.deq = nullptr;
+      a.Tm = pv;
+      if (int rc = run_pass_b<double>(f, a, PASS_B_EXPAND, s)) return rc;
+      if (int rc = normal_product(w)) return rc;
+      GLM_CHECK(launch_ne_step(f->d_inst(), f->d_blk(), p.B, f->at<double>(p.o_R), Oinv, Tm,
+                               beta, rv, zv, pv, f->d_st(), f->d_active(), icount, tol,
+                               max_iter, s));
+      ++f->launches;
+    }
+  }
+  f->stats.outer_steps = 1;
+  f->stats.launches = f->launches;
+  return map_info_and_stats(f, info, iters, false, s);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1432,6 +1515,22 @@ int glm_gls_solve(glm_factor* f, const double* Omega, const double* y, const dou
     return solve_reduced(f, Omega, y, r, tol, max_iter, beta, u, uc, info, iters, stream);
   if (f->p.sumCK > 0 && !r) return GLM_EINVAL;
   return solve_driver(f, Omega, y, nullptr, r, tol, max_iter, beta, u, uc, info, iters, stream);
+}
+
+int glm_gls_solve_ne(glm_factor* f, const double* Omega, const double* y, double tol,
+                     int32_t max_iter, double* beta, int32_t* info, int32_t* iters,
+                     hipStream_t stream) {
+  if (!f || !Omega || !y || !beta) return GLM_EINVAL;
+  if (!(tol >= 0.0)) return GLM_EINVAL;
+  if (!f->reduced) return ne_driver(f, Omega, y, tol, max_iter, beta, info, iters, stream);
+  // the GLS estimate of the reduced model is that of the full model
+  if (f->sub->p.sumCK > 0) return GLM_EUNSUPPORTED;
+  if (int rc = timed_gemm1(f, y, f->at<double>(f->rp.o_yr), stream)) return rc;
+  const int rc = ne_driver(f->sub, Omega, f->at<double>(f->rp.o_yr), tol, max_iter, beta, info,
+                           iters, stream);
+  f->stats = f->sub->stats;
+  ++f->stats.launches;
+  return rc;
 }
 
 int glm_gls_backward(glm_factor* f, const double* Omega, const double* beta, const double* u,

@@ -254,6 +254,16 @@ hipError_t launch_red_grad(const RedDesc* d, int B, int maxM, const InstDesc* si
                           const int* colblk, const double* L, const double* U,
                           const double* beta, const double* lb, double* part, double* dOm,
                           double* dX, hipStream_t s);
+hipError_t launch_ne_oinv(const InstDesc* insts, int B, const double* Om, double* A,
+                          double* Oinv, RhsState* st, int* inst_active, hipStream_t s);
+hipError_t launch_ne_start(const InstDesc* insts, const BlockDesc* blks, int B, const double* R,
+                           const double* Oinv, const double* Tm, double* x, double* r,
+                           double* z, double* p, RhsState* st, int* inst_active, int* icount,
+                           hipStream_t s);
+hipError_t launch_ne_step(const InstDesc* insts, const BlockDesc* blks, int B, const double* R,
+                          const double* Oinv, const double* Tm, double* x, double* r,
+                          double* z, double* p, RhsState* st, int* inst_active, int* icount,
+                          double tol, int maxit_user, hipStream_t s);
 hipError_t launch_grad(const InstDesc* insts, const TileDesc* tiles, int ntiles, int B,
                        const int* colblk, const double* L, const double* U,
                        const double* beta, const double* lb, double* part, double* dOm,

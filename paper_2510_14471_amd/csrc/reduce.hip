@@ -27,6 +27,7 @@
 //   k_red_grad_omega_part/_reduce, k_red_grad_x   dOmega and dX of the full model.
 #include "glm.h"
 #include "glm_internal.h"
+#include "ginv.h"
 #include "qr_panel.h"
 
 #include <algorithm>
@@ -659,124 +660,15 @@ k_red_gemm_nn(const RedDesc* __restrict__ descs, const GemmTile* __restrict__ ti
   }
 }
 
-// ---------------------------------------------------------------------------
-// Omega^g: a generalized inverse of the PSD Omega (Omega Omega^g Omega = Omega)
-// by Cholesky with diagonal pivoting, stopped when the largest remaining
-// diagonal is at most 16 G eps trace(Omega) (the rank r); with L the r x r
-// factor and Pm the pivoting, Omega^g = Pm [L^-T L^-1, 0; 0, 0] Pm^T, the
-// inverse when r = G.  One workgroup per instance, in global memory
-// (A: G x G work area).  sing[b] = 1 when r < G.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
+// Omega^g, a generalized inverse of the PSD Omega (Omega Omega^g Omega =
+// Omega; the inverse when Omega is positive definite), one workgroup per
+// instance (A: G x G work area).  sing[b] = 1 when Omega is singular.
+__global__ void __launch_bounds__(GINV_NT)
 k_red_ginv(const RedDesc* __restrict__ descs, const double* __restrict__ Om,
            double* __restrict__ A, double* __restrict__ Og, int* __restrict__ sing) {
   const RedDesc d = descs[blockIdx.x];
-  const int G = d.G, tid = threadIdx.x;
-  double* a = A + d.om_off;
-  const double* o = Om + d.om_off;
-  double* og = Og + d.om_off;
-  __shared__ int perm[256];
-  __shared__ double dinv[256];
-  __shared__ double s_piv, s_tol;
-  __shared__ int s_j;
-  for (int e = tid; e < G * G; e += 256) a[e] = o[e];
-  for (int i = tid; i < G; i += 256) perm[i] = i;
-  if (tid < 64) {
-    double tr = 0.0;
-    for (int i = tid; i < G; i += 64) tr += fabs(o[(int64_t)i * G + i]);
-    tr = wave_sum(tr);
-    if (tid == 0) s_tol = 16.0 * G * 2.220446049250313e-16 * tr;
-  }
-  __syncthreads();
-  int r = G;
-  for (int k = 0; k < G; ++k) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bj = k;
-      for (int j = k + tid; j < G; j += 64) {
-        const double v = a[(int64_t)j * G + j];
-        if (v > best) {
-          best = v;
-          bj = j;
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oj = __shfl_xor(bj, off, 64);
-        if (ob > best || (ob == best && oj < bj)) {
-          best = ob;
-          bj = oj;
-        }
-      }
-      if (tid == 0) {
-        s_piv = best;
-        s_j = bj;
-      }
-    }
-    __syncthreads();
-    if (!(s_piv > s_tol)) {
-      r = k;
-      break;
-    }
-    const int j = s_j;
-    if (j != k) {
-      for (int c = tid; c < G; c += 256) {
-        const double t0 = a[(int64_t)k * G + c];
-        a[(int64_t)k * G + c] = a[(int64_t)j * G + c];
-        a[(int64_t)j * G + c] = t0;
-      }
-      __syncthreads();
-      for (int rr = k + tid; rr < G; rr += 256) {
-        const double t0 = a[(int64_t)rr * G + k];
-        a[(int64_t)rr * G + k] = a[(int64_t)rr * G + j];
-        a[(int64_t)rr * G + j] = t0;
-      }
-      if (tid == 0) {
-        const int pk = perm[k];
-        perm[k] = perm[j];
-        perm[j] = pk;
-      }
-      __syncthreads();
-    }
-    const double lkk = sqrt(a[(int64_t)k * G + k]);
-    __syncthreads();
-    for (int i = k + 1 + tid; i < G; i += 256) a[(int64_t)i * G + k] /= lkk;
-    if (tid == 0) {
-      a[(int64_t)k * G + k] = lkk;
-      dinv[k] = 1.0 / lkk;
-    }
-    __syncthreads();
-    const int w = G - k - 1;
-    for (int e = tid; e < w * w; e += 256) {
-      const int i = k + 1 + e / w, c = k + 1 + e % w;
-      a[(int64_t)i * G + c] -= a[(int64_t)i * G + k] * a[(int64_t)c * G + k];
-    }
-    __syncthreads();
-  }
-  // column c of L^-1 (rows i > c) into the upper triangle: a[c][i] = (L^-1)[i][c]
-  for (int c = tid; c < r; c += 256) {
-    for (int i = c + 1; i < r; ++i) {
-      double s = a[(int64_t)i * G + c] * dinv[c];
-      for (int kk = c + 1; kk < i; ++kk) s += a[(int64_t)i * G + kk] * a[(int64_t)c * G + kk];
-      a[(int64_t)c * G + i] = -s * dinv[i];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < G * G; e += 256) {
-    const int p = e / G, q = e % G;
-    double s = 0.0;
-    if (p < r && q < r) {
-      const int lo = p > q ? p : q;
-      for (int kk = lo; kk < r; ++kk) {
-        const double lp = (kk == p) ? dinv[p] : a[(int64_t)p * G + kk];
-        const double lq = (kk == q) ? dinv[q] : a[(int64_t)q * G + kk];
-        s += lp * lq;
-      }
-    }
-    og[(int64_t)perm[p] * G + perm[q]] = s;
-  }
-  if (tid == 0) sing[d.inst] = (r < G) ? 1 : 0;
+  const int r = psd_ginv(d.G, Om + d.om_off, A + d.om_off, Og + d.om_off);
+  if (threadIdx.x == 0) sing[d.inst] = (r < d.G) ? 1 : 0;
 }
 
 // U = (Y - [X_i beta_i]) Omega^g.  Workgroup (instance, URC rows), taken in
@@ -1024,7 +916,7 @@ hipError_t launch_red_gemm_tn(const RedDesc* d, const GemmTile* tiles, int ntile
 hipError_t launch_red_ginv(const RedDesc* d, int B, const double* Om, double* A, double* Og,
                           int* sing, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_red_ginv, dim3(B), dim3(256), 0, s, d, Om, A, Og, sing);
+  hipLaunchKernelGGL(k_red_ginv, dim3(B), dim3(GINV_NT), 0, s, d, Om, A, Og, sing);
   return hipGetLastError();
 }
 

@@ -175,6 +175,16 @@ class SURSolver:
                            stream)
         return beta, u, uc, info, iters
 
+    def solve_ne(self, Omega, y, tol=1e-12, max_iter=0, stream=None):
+        """CG on the normal equations (block-Jacobi preconditioner), FP64:
+        (beta, info, iters).  The comparator of the PCG-Aug estimator."""
+        lay = self.layout
+        beta = torch.empty(lay.off_b[-1], dtype=torch.float64, device=self.device)
+        info = torch.empty(lay.n_rhs, dtype=torch.int32, device=self.device)
+        iters = torch.empty(lay.n_rhs, dtype=torch.int32, device=self.device)
+        _lib.glm_gls_solve_ne(self.handle, Omega, y, tol, max_iter, beta, info, iters, stream)
+        return beta, info, iters
+
     def backward(self, Omega, beta, u, g_beta, g_u=None, tol=1e-12, max_iter=0,
                  want_dOmega=True, want_dX=True, stream=None):
         lay = self.layout

@@ -13,6 +13,7 @@ from .sur import (  # noqa: F401
     config3,
     config4,
     small_batch,
+    mc_sur,
     e1_setup,
     e2_setup,
     tiny_integer_sur,

@@ -310,6 +310,36 @@ def small_batch(seed: int = 7, B: int = 6, G_rng=(1, 6), M_rng=(20, 300),
     return SURBatch(out, name=f"small_batch_s{seed}")
 
 
+def mc_sur(seed: int = 21, B: int = 256, K: int = 16, G: int = 4, M: int = 20, ni: int = 5,
+           eigvals=(0.01, 0.1, 10.0, 50.0)) -> SURBatch:
+    """SUR counterpart of the Monte Carlo experiment comparing the PCG-Aug
+    and PCG-NE estimators: m = G M = 80 observations and n = G ni = 20
+    coefficients; Omega = V diag(eigvals) V^T with V a random orthogonal
+    matrix, so that Sigma = Omega (x) I_M has the four eigenvalues 0.01, 0.1,
+    10 and 50, each M times; the regressors follow the recipe of the
+    convergence experiment (a constant first column, other entries of
+    variance m).  X, Omega and beta are drawn once and shared by all B
+    instances; each of the B K right-hand sides is one replication
+    y = X beta + eps with eps ~ N(0, Sigma)."""
+    rng = np.random.default_rng(seed)
+    n_i = [ni] * G
+    m = G * M
+    W = rng.standard_normal((M, G * ni)) * np.sqrt(m)
+    W[:, ::ni] = 1.0
+    V, _ = np.linalg.qr(rng.standard_normal((G, G)))
+    Omega = (V * np.asarray(eigvals, dtype=np.float64)) @ V.T
+    Omega = 0.5 * (Omega + Omega.T)
+    beta = 1.0 + rng.standard_normal((G * ni, 1))
+    F = np.linalg.cholesky(Omega)
+    out = []
+    for _ in range(B):
+        E = _noise_from_factor(rng, M, F, K)
+        Y = _responses(W, n_i, np.repeat(beta, K, axis=1), E)
+        out.append(SURInstance(n_i=list(n_i), W=W, Omega=Omega, Y=Y,
+                               beta_true=np.repeat(beta, K, axis=1), noise=E))
+    return SURBatch(out, name=f"mc_sur_s{seed}")
+
+
 CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
 
 
