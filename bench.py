@@ -16,7 +16,10 @@ on (outside the timed region) gives the HIP-event durations and algorithmic
 bytes of the projection passes for the roofline.  The single large SUR
 (G = 50, M = 1e4), the differentiation workload (G = 20, M = 2e4) and the
 singular, restricted workload (G = 100, M = 5e4, rank G - 2, 10 restrictions)
-are measured the same way through the model reduction (`configs`).
+are measured the same way through the model reduction (`configs`).  The
+comparator PCG-NE (CG on the normal equations) is timed on the headline
+workload (`pcg_ne`), and the Monte Carlo comparison of the two estimators
+runs at 4096 replications (`montecarlo`).
 
 Prints one JSON line.
 """
@@ -112,6 +115,8 @@ def main():
                     help="skip the runs without the model reduction")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the single large, differentiation and singular workloads")
+    ap.add_argument("--no-ne", action="store_true",
+                    help="skip the PCG-NE comparator and the Monte Carlo study")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -224,6 +229,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_configs:
         out["configs"] = other_configs(glm, torch, synth, args)
+    if not args.no_ne:
+        out["pcg_ne"] = ne_comparator(glm, torch, synth, args)
+        out["montecarlo"] = montecarlo(glm, torch, synth)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -278,6 +286,92 @@ def other_configs(glm, torch, synth, args):
         del runner, d
         torch.cuda.empty_cache()
     return out
+
+
+def ne_comparator(glm, torch, synth, args):
+    """PCG-NE (CG on the normal equations, block-Jacobi preconditioner, FP64)
+    on the headline workload through the same model reduction: one step =
+    reduction QR + per-block QR + the normal-equation solves, stopped at
+    ||r|| <= 1e-13 ||b||."""
+    import numpy as np
+    from oracle import gls as ogls
+    insts = list(synth.config2(B=args.instances))
+    lay, d = glm.pack_instances(insts)
+    s = glm.SURSolver(lay, "fp64", reduce=True)
+
+    def step():
+        s.factor(d["X"], d["Rc"])
+        return s.solve_ne(d["Omega"], d["y"], tol=1e-13, max_iter=0)
+
+    step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = 0
+    for _ in range(args.steps):
+        beta, info, iters = step()
+        its += s.stats()["pcg_iterations"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    infos = info.cpu().numpy()
+    betas = glm.unpack(lay, beta, "beta")
+    sample = list(range(0, len(insts), max(1, len(insts) // max(1, args.check))))[: args.check]
+    eb = max(rel(betas[b][:, k], ogls.sur_gls(insts[b])[0][:, k])
+             for b in sample for k in range(insts[b].K))
+    out = {"solves_per_s": round(lay.n_rhs * args.steps / dt, 2),
+           "ms_per_step": round(1000 * dt / args.steps, 2),
+           "iterations_per_s": round(its / dt, 1),
+           "mean_iterations": round(its / args.steps / lay.n_rhs, 1),
+           "converged": f"{int(np.sum(infos == 0))}/{lay.n_rhs}",
+           "max_rel_err_beta": eb}
+    log(f"pcg-ne: {out}")
+    s.close()
+    del s, d
+    torch.cuda.empty_cache()
+    return out
+
+
+def montecarlo(glm, torch, synth, iters=(1, 2, 3, 4, 6, 8, 12, 16, 20)):
+    """The Monte Carlo comparison of the PCG-Aug and PCG-NE estimators
+    (section on the statistical properties of the PCG-Aug estimator) at
+    4096 replications of its SUR counterpart (m = 80, n = 20, Sigma with
+    eigenvalues 0.01, 0.1, 10, 50): for each iteration count, the largest
+    |mean error| / standard error over the coefficients, the RMSE of beta,
+    and the mean and 2.5/97.5 % quantiles of the error of beta_2."""
+    import numpy as np
+    insts = list(synth.mc_sur(seed=21, B=256, K=16))
+    lay, d = glm.pack_instances(insts)
+    truth = np.array([inst.beta_true[:, k] for inst in insts for k in range(inst.K)])
+    res = {"workload": "mc_sur_m80_n20: G=4, M=20, n_i=5, Omega eigenvalues "
+                       "(0.01, 0.1, 10, 50); X, Omega, beta fixed, y redrawn",
+           "replications": int(truth.shape[0]), "iterations": list(iters)}
+    t = time.perf_counter()
+    for name in ("pcg_aug", "pcg_ne"):
+        s = glm.SURSolver(lay, "fp64")
+        s.factor(d["X"], d["Rc"])
+        rows = {"max_abs_z": [], "rmse": [], "beta2_mean_err": [], "beta2_q025": [],
+                "beta2_q975": []}
+        for i in iters:
+            if name == "pcg_aug":
+                beta = s.solve(d["Omega"], d["y"], d["r"], tol=0.0, max_iter=i)[0]
+            else:
+                beta = s.solve_ne(d["Omega"], d["y"], tol=0.0, max_iter=i)[0]
+            bs = glm.unpack(lay, beta, "beta")
+            est = np.array([bs[b][:, k] for b, inst in enumerate(insts) for k in range(inst.K)])
+            e = est - truth
+            z = np.abs(e.mean(0)) / (e.std(0, ddof=1) / np.sqrt(e.shape[0]))
+            rows["max_abs_z"].append(round(float(z.max()), 2))
+            rows["rmse"].append(float(np.sqrt(np.mean(np.sum(e * e, axis=1)))))
+            rows["beta2_mean_err"].append(float(e[:, 1].mean()))
+            rows["beta2_q025"].append(float(np.quantile(e[:, 1], 0.025)))
+            rows["beta2_q975"].append(float(np.quantile(e[:, 1], 0.975)))
+        res[name] = rows
+        s.close()
+    res["seconds"] = round(time.perf_counter() - t, 2)
+    log(f"montecarlo: PCG-Aug max|z| {res['pcg_aug']['max_abs_z']}, "
+        f"PCG-NE max|z| {res['pcg_ne']['max_abs_z']}")
+    del d
+    torch.cuda.empty_cache()
+    return res
 
 
 def kernel_sources_sha256():
