@@ -206,7 +206,10 @@ int glm_qr_factor_static(const glm_shape* shape, glm_precision prec, const doubl
  *   r         device, k_b x K_b per restricted instance, or NULL if none
  *   tol       GLM_FP64: stop when sqrt(c_i / c_1) <= tol (c_i = r_i^T Pi r_i);
  *             GLM_MIXED: stop when the double-precision residual of eq. aug1,
- *             ||[y - Sigma u - X beta ; -X^T u]|| <= tol * ||y||
+ *             ||[y - Sigma u - X beta ; -Q^T u]|| <= tol * ||y||, its lower
+ *             block taken in the coordinates of the orthonormal factors
+ *             (X_i^T u = R_i^T Q_i^T u), so that the test does not depend on
+ *             the scaling of X's columns
  *   max_iter  PCG iteration limit per (instance, rhs) (per inner solve for
  *             GLM_MIXED); <= 0 selects m - n + 1 (Algorithm PCG-Aug bound)
  *   beta      device out, n_b x K_b per instance

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -197,7 +198,7 @@ int validate(const glm_shape* s) {
     if (kc > 64) return GLM_EUNSUPPORTED;
     // column slots per thread of the projection passes: up to 4 for any K,
     // up to 8 (n <= 2048) when K <= 4
-    if (n > 8 * NT) return GLM_EUNSUPPORTED;
+    if (n > NMAX_INST) return GLM_EUNSUPPORTED;
     const int slots = (int)((n + NT - 1) / NT);
     if (slots > 4 && pick_kc(K) > 4) return GLM_EUNSUPPORTED;
     if ((int64_t)G * G > 64 * 1024) return GLM_EUNSUPPORTED;
@@ -522,7 +523,7 @@ struct RedPlan {
   size_t o_desc = 0, o_W = 0, o_tau = 0, o_T = 0, o_Tleaf = 0, o_Stk = 0, o_Q1 = 0, o_Xr = 0,
          o_yr = 0, o_ur = 0,
          o_dd = 0, o_Og = 0, o_Ow = 0, o_sing = 0, o_t1 = 0, o_t2 = 0, o_Zp = 0, o_lb = 0,
-         o_sub = 0, sub_bytes = 0, total = 0;
+         o_cexp = 0, o_sub = 0, sub_bytes = 0, total = 0;
 };
 
 // Tile table of a batched product: every instance's output tiles (rows x
@@ -644,6 +645,7 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
   r.o_t2 = take(sizeof(GemmTile) * r.t2.size());
   r.o_W = take(8 * r.sumMn);
   r.o_tau = take(8 * r.sumn);
+  r.o_cexp = take(4 * r.sumn);
   r.o_T = take(8 * r.sumT);
   r.o_Tleaf = take(8 * r.sumLeaf);
   r.o_Stk = take(8 * r.sumLeaf);
@@ -1061,7 +1063,8 @@ int solve_driver(glm_factor* f, const double* Om, const double* y, const double*
                                         f->at<double>(p.o_Tpart), Tm64,
                                         p.cfg[1].rowpass, s));
       GLM_CHECK(launch_to_float(y64, yf, p.sumMGK, s));
-      GLM_CHECK(launch_outer_check(f->d_inst(), p.B, f->d_active(), f->d_st(),
+      GLM_CHECK(launch_outer_check(f->d_inst(), f->d_blk(), f->at<double>(p.o_R), p.B,
+                                   f->d_active(), f->d_st(),
                                    f->at<int>(p.o_ost), f->at<double>(p.o_cpart),
                                    f->at<double>(p.o_ypart), Tm64, -1.0, h2, f->Rc, rvec,
                                    beta_out, wc64, f->at<double>(p.o_rho0),
@@ -1285,7 +1288,9 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
   if (!e)
     e = hipMemcpyAsync(f->ws + r.o_t2, r.t2.data(), sizeof(GemmTile) * r.t2.size(),
                        hipMemcpyHostToDevice, stream);
-  if (!e) e = hipMemcpyAsync(W, X, 8 * r.sumMn, hipMemcpyDeviceToDevice, stream);
+  // W = X with power-of-two column scaling (undone in the extracted R rows)
+  if (!e) e = launch_fill<int>(f->at<int>(r.o_cexp), r.sumn, INT_MIN, stream);
+  if (!e) e = launch_red_equilibrate(dd, r.B, r.maxM, X, f->at<int>(r.o_cexp), W, stream);
   for (int p = 0; p < r.maxpan && !e; ++p)
     // trailing columns: n - c0 - w, with w < 32 where kr = min(M, n) ends the
     // panel early, so the bound is n - c0
@@ -1295,7 +1300,7 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
   for (int p = r.maxpan - 1; p >= 0 && !e; --p)
     e = launch_red_q1_panel(dd, r.B, p, r.maxseg, r.maxMr - p * RED_PANEL, W, Tleaf, Stk, T, Q1,
                             stream);
-  if (!e) e = launch_red_extract(dd, r.B, W, f->at<double>(r.o_Xr), stream);
+  if (!e) e = launch_red_extract(dd, r.B, W, f->at<int>(r.o_cexp), f->at<double>(r.o_Xr), stream);
   if (e != hipSuccess) {
     delete f;
     return GLM_EHIP;

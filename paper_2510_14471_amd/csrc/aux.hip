@@ -115,7 +115,8 @@ __global__ void k_copy_tc(const InstDesc* __restrict__ insts, int B, const T* __
 // and the outer stopping test.  Rhs that still need work become ST_ACTIVE for
 // the next inner solve, the others ST_IDLE; ost keeps the outer outcome.
 __global__ void __launch_bounds__(NT)
-k_outer_check(const InstDesc* __restrict__ insts, int* __restrict__ inst_active,
+k_outer_check(const InstDesc* __restrict__ insts, const BlockDesc* __restrict__ blks,
+              const double* __restrict__ R, int* __restrict__ inst_active,
               RhsState* __restrict__ st, int* __restrict__ ost,
               const double* __restrict__ rpart, const double* __restrict__ ypart,
               const double* __restrict__ XtW, double xtw_sign, const double* __restrict__ h2,
@@ -142,8 +143,30 @@ k_outer_check(const InstDesc* __restrict__ insts, int* __restrict__ inst_active,
       for (int q = 0; q < kc; ++q)
         v -= Rc[in.rc_off + (int64_t)q * n + c] * wc[in.c_off + (int64_t)q * K + k];
       rho0[bi] = v;
-      acc_r += v * v;
-      if (h2) acc_y += h2[bi] * h2[bi];
+    }
+    __syncthreads();
+    // the lower block is measured in the coordinates of the orthonormal
+    // factor: with X_i = Q_i R_i, X_i^T u = h_i is R_i^T (Q_i^T u) = h_i, so
+    // its residual is R_i^-T rho0_i (for h2 = 0: Q^T u), which does not
+    // change when the columns of X are scaled
+    for (int i = threadIdx.x; i < in.G; i += NT) {
+      const BlockDesc bd = blks[in.blk0 + i];
+      const double* Ri = R + bd.r_off;
+      const int ni = bd.ni;
+      const int64_t o = in.b_off + (int64_t)bd.col * K + k;
+      double zr[QR_NMAX], zh[QR_NMAX];
+      for (int a = 0; a < ni; ++a) {
+        double sr = rho0[o + (int64_t)a * K];
+        double sh = h2 ? h2[o + (int64_t)a * K] : 0.0;
+        for (int c = 0; c < a; ++c) {
+          sr -= Ri[c * ni + a] * zr[c];
+          sh -= Ri[c * ni + a] * zh[c];
+        }
+        zr[a] = sr / Ri[a * ni + a];
+        zh[a] = sh / Ri[a * ni + a];
+        acc_r += zr[a] * zr[a];
+        acc_y += zh[a] * zh[a];
+      }
     }
     for (int q = wv; q < kc; q += NT / 64) {
       double s = 0.0;
@@ -382,14 +405,16 @@ template hipError_t launch_copy_tc<double>(const InstDesc*, int, const double*, 
 template hipError_t launch_copy_tc<float>(const InstDesc*, int, const float*, double*,
                                           hipStream_t);
 
-hipError_t launch_outer_check(const InstDesc* insts, int B, int* inst_active, RhsState* st,
+hipError_t launch_outer_check(const InstDesc* insts, const BlockDesc* blks, const double* R,
+                              int B, int* inst_active, RhsState* st,
                               int* ost, const double* rpart, const double* ypart,
                               const double* XtW, double xtw_sign, const double* h2,
                               const double* Rc,
                               const double* rvec, const double* beta, const double* wc,
                               double* rho0, double* rhoc, double tol, int step,
                               int last_step, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_check, dim3(B), dim3(NT), 0, s, insts, inst_active, st, ost,
+  hipLaunchKernelGGL(k_outer_check, dim3(B), dim3(NT), 0, s, insts, blks, R, inst_active, st,
+                     ost,
                      rpart, ypart, XtW, xtw_sign, h2, Rc, rvec, beta, wc, rho0, rhoc, tol, step,
                      last_step);
   return hipGetLastError();

@@ -9,6 +9,7 @@ namespace glm {
 constexpr int NT = 256;          // threads per workgroup of the tile kernels
 constexpr int KMAX = 16;         // right-hand sides per instance
 constexpr int QR_NMAX = 64;      // widest block the QR kernel factors
+constexpr int NMAX_INST = 8 * NT; // widest instance (n = sum of n_i) of any path
 
 // Per-(instance, rhs) iteration status.
 enum : int {
@@ -212,7 +213,8 @@ hipError_t launch_activate(const InstDesc* insts, int B, const RhsState* st, int
 template <typename T>
 hipError_t launch_copy_tc(const InstDesc* insts, int B, const T* Tm, double* wc,
                           hipStream_t s);
-hipError_t launch_outer_check(const InstDesc* insts, int B, int* inst_active, RhsState* st,
+hipError_t launch_outer_check(const InstDesc* insts, const BlockDesc* blks, const double* R,
+                              int B, int* inst_active, RhsState* st,
                               int* ost, const double* rpart, const double* ypart,
                               const double* XtW, double xtw_sign, const double* h2,
                               const double* Rc,
@@ -237,8 +239,10 @@ hipError_t launch_red_q1_panel(const RedDesc* d, int B, int panel, int maxseg, i
                               const double* W, const double* Tleaf, const double* Stk,
                               const double* T, double* Q1, hipStream_t s);
 hipError_t launch_red_qinit(const RedDesc* d, int B, double* Q1, hipStream_t s);
-hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, double* Xr,
-                             hipStream_t s);
+hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, const int* ex,
+                             double* Xr, hipStream_t s);
+hipError_t launch_red_equilibrate(const RedDesc* d, int B, int maxM, const double* X, int* ex,
+                                  double* W, hipStream_t s);
 hipError_t launch_red_gemm_tn(const RedDesc* d, const GemmTile* tiles, int ntiles,
                              const double* Q1, const double* Y, double* Yr, hipStream_t s);
 hipError_t launch_red_ginv(const RedDesc* d, int B, const double* Om, double* A, double* Og,

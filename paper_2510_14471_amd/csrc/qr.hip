@@ -12,6 +12,8 @@
 #include "glm_internal.h"
 #include "qr_panel.h"
 
+#include <cfloat>
+#include <climits>
 #include <cmath>
 
 namespace glm {
@@ -40,6 +42,76 @@ __device__ void block_sum(double (&dots)[NMAX], int lo, int cols,
   __syncthreads();
 }
 
+// Column equilibration by powers of two.  Column c of the rows x cols block
+// (cols <= 64) is multiplied by 2^-ex[c], ex[c] the binary exponent of its
+// largest magnitude (frexp convention; 0 for a column of zeros).  The
+// scaling is exact and Householder QR commutes with it: the reflectors and
+// Q of the scaled block are those of the block itself, and R's column c
+// comes out multiplied by 2^-ex[c].  With every column's largest entry in
+// [1/2, 1) the norms of the factorization neither overflow nor underflow,
+// whatever the scale of the data, and the zero-subcolumn threshold of the
+// reflectors acts relative to the column's magnitude.
+__device__ void equilibrate_cols(double* __restrict__ a0, int rows, int cols, int ld,
+                                 int* __restrict__ ex, int (*part)[QW]) {
+  const int tid = threadIdx.x, c = tid & 63, rg = tid >> 6;
+  int e = INT_MIN;
+  if (c < cols)
+    for (int t = rg; t < rows; t += QW) {
+      const double v = fabs(a0[(int64_t)t * ld + c]);
+      if (v > 0.0 && v <= DBL_MAX) {
+        int q;
+        (void)frexp(v, &q);
+        e = max(e, q);
+      }
+    }
+  part[c][rg] = e;
+  __syncthreads();
+  if (tid < cols) {
+    int m = INT_MIN;
+#pragma unroll
+    for (int q = 0; q < QW; ++q) m = max(m, part[tid][q]);
+    ex[tid] = (m == INT_MIN) ? 0 : m;
+  }
+  __syncthreads();
+  if (c < cols && ex[c] != 0)
+    for (int t = rg; t < rows; t += QW)
+      a0[(int64_t)t * ld + c] = ldexp(a0[(int64_t)t * ld + c], -ex[c]);
+  __syncthreads();
+}
+
+// R (upper triangle of the first cols rows of the factored, equilibrated
+// block) out with the column scaling undone, and the rank check on the
+// equilibrated factor: a diagonal entry at most eps max(rows, cols) ||R||_F
+// flags the block.  Column scaling does not change the column space, so the
+// check is made where every column has unit scale.
+__device__ void r_out_and_rank(const QRJob& job, const double* __restrict__ a0, int rows,
+                               int cols, int ld, const int* __restrict__ ex,
+                               double* __restrict__ Rout, int* __restrict__ flags,
+                               double* fro2) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *fro2 = 0.0;
+  __syncthreads();
+  double loc = 0.0;
+  for (int e = tid; e < cols * cols; e += QNT) {
+    const int r = e / cols, cc = e % cols;
+    const double v = (cc >= r) ? a0[(int64_t)r * ld + cc] : 0.0;
+    if (job.r_off >= 0) Rout[job.r_off + e] = ldexp(v, ex[cc]);
+    loc += v * v;
+  }
+  loc = wave_sum(loc);
+  if ((tid & 63) == 0) atomicAdd(fro2, loc);
+  __syncthreads();
+  if (tid == 0) {
+    const double tolr = 2.220446049250313e-16 * (double)(rows > cols ? rows : cols) *
+                        sqrt(*fro2);
+    int bad = 0;
+    for (int r = 0; r < cols; ++r)
+      if (!(fabs(a0[(int64_t)r * ld + r]) > tolr)) bad = 1;
+    if (job.flag >= 0) flags[job.flag] = bad;
+  }
+  __syncthreads();
+}
+
 template <int NMAX>
 __global__ void __launch_bounds__(QNT)
 k_qr(const QRJob* __restrict__ jobs, double* __restrict__ A,
@@ -56,8 +128,11 @@ k_qr(const QRJob* __restrict__ jobs, double* __restrict__ A,
   __shared__ double par[3];          // beta, tau, scale of the current reflector
   __shared__ double fro2;
 
+  __shared__ int ex[NMAX];
+  __shared__ int part[64][QW];
   const int tid = threadIdx.x;
   double dots[NMAX];
+  equilibrate_cols(a0, rows, cols, ld, ex, part);
 
   // ---- factorization: pass p applies reflector p-1 and builds reflector p --
   for (int p = 0; p <= cols; ++p) {
@@ -135,27 +210,7 @@ k_qr(const QRJob* __restrict__ jobs, double* __restrict__ A,
   __syncthreads();
 
   // ---- R out (upper triangle of the first cols rows), rank check ---------
-  if (tid == 0) fro2 = 0.0;
-  __syncthreads();
-  double loc = 0.0;
-  for (int e = tid; e < cols * cols; e += QNT) {
-    const int r = e / cols, c = e % cols;
-    const double v = (c >= r) ? a0[(int64_t)r * ld + c] : 0.0;
-    if (job.r_off >= 0) Rout[job.r_off + e] = v;
-    loc += v * v;
-  }
-  loc = wave_sum(loc);
-  if ((tid & 63) == 0) atomicAdd(&fro2, loc);
-  __syncthreads();
-  if (tid == 0) {
-    const double tolr = 2.220446049250313e-16 * (double)(rows > cols ? rows : cols) *
-                        sqrt(fro2);
-    int bad = 0;
-    for (int r = 0; r < cols; ++r)
-      if (!(fabs(a0[(int64_t)r * ld + r]) > tolr)) bad = 1;
-    if (job.flag >= 0) flags[job.flag] = bad;
-  }
-  __syncthreads();
+  r_out_and_rank(job, a0, rows, cols, ld, ex, Rout, flags, &fro2);
 
   // ---- explicit thin Q, backward accumulation of the reflectors ---------
   // pass j: apply H(j) (w from the previous pass) to columns > j, finalize
@@ -238,33 +293,16 @@ k_qr32(const QRJob* __restrict__ jobs, double* __restrict__ A, double* __restric
   double* dsum = sh.dsum;
   const double* tau_s = sh.tau_s;
 
+  __shared__ int ex[32];
+  __shared__ int part[64][QW];
   const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
   const bool colok = c < cols;
 
+  equilibrate_cols(a0, rows, cols, ld, ex, part);
   qr32_factor<QNT, K32_U>(a0, rows, cols, ld, sh);
 
   // ---- R out (upper triangle of the first cols rows), rank check ---------
-  if (tid == 0) fro2 = 0.0;
-  __syncthreads();
-  double loc = 0.0;
-  for (int e = tid; e < cols * cols; e += QNT) {
-    const int r = e / cols, cc = e % cols;
-    const double v = (cc >= r) ? a0[(int64_t)r * ld + cc] : 0.0;
-    if (job.r_off >= 0) Rout[job.r_off + e] = v;
-    loc += v * v;
-  }
-  loc = wave_sum(loc);
-  if ((tid & 63) == 0) atomicAdd(&fro2, loc);
-  __syncthreads();
-  if (tid == 0) {
-    const double tolr = 2.220446049250313e-16 * (double)(rows > cols ? rows : cols) *
-                        sqrt(fro2);
-    int bad = 0;
-    for (int r = 0; r < cols; ++r)
-      if (!(fabs(a0[(int64_t)r * ld + r]) > tolr)) bad = 1;
-    if (job.flag >= 0) flags[job.flag] = bad;
-  }
-  __syncthreads();
+  r_out_and_rank(job, a0, rows, cols, ld, ex, Rout, flags, &fro2);
 
   // ---- explicit thin Q, backward accumulation of the reflectors ---------
   for (int j = cols - 1; j >= 0; --j) {

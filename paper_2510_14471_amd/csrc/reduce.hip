@@ -31,6 +31,8 @@
 #include "qr_panel.h"
 
 #include <algorithm>
+#include <cfloat>
+#include <climits>
 #include <cmath>
 
 namespace glm {
@@ -38,6 +40,10 @@ namespace glm {
 namespace {
 
 constexpr int RP = RED_PANEL;
+constexpr int EQ_ROWS = 512;   // rows per workgroup of the column equilibration
+
+// exponent of a column's scaling (INT_MIN marks a column of zeros: no scaling)
+__device__ __forceinline__ int col_exp(int e) { return e == INT_MIN ? 0 : e; }
 
 // V[r][j] of panel rows r (relative to the panel's first row): the unit
 // diagonal and zeros above it are implicit in the stored factorization.
@@ -490,13 +496,74 @@ k_red_qinit(const RedDesc* __restrict__ descs, double* __restrict__ Q1) {
 // Reduced regressors Xr[t][c] = R[t][c] (c >= t, t < kr; zero elsewhere).
 __global__ void __launch_bounds__(QNT)
 k_red_extract(const RedDesc* __restrict__ descs, const double* __restrict__ W,
-              double* __restrict__ Xr) {
+              const int* __restrict__ ex, double* __restrict__ Xr) {
   const RedDesc d = descs[blockIdx.x];
   const int64_t cnt = (int64_t)d.Mr * d.n;
   for (int64_t e = threadIdx.x; e < cnt; e += QNT) {
     const int t = (int)(e / d.n), c = (int)(e % d.n);
-    Xr[d.xr_off + e] = (t < d.kr && c >= t) ? W[d.w_off + e] : 0.0;
+    Xr[d.xr_off + e] =
+        (t < d.kr && c >= t) ? ldexp(W[d.w_off + e], col_exp(ex[d.tau_off + c])) : 0.0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Column equilibration of W by powers of two.  Column c of an instance is
+// multiplied by 2^-e_c, e_c the binary exponent of its largest magnitude
+// (frexp convention).  The scaling is exact and the QR commutes with it: the
+// reflectors, T factors and Q1 of the scaled W are those of W, while the rows
+// of R come out with column c multiplied by 2^-e_c and are scaled back by
+// k_red_extract.  With every column's largest entry in [1/2, 1) the norms of
+// the factorization neither overflow nor underflow whatever the scale of the
+// data.  Workgroup (instance, EQ_ROWS rows); the exponents are combined with
+// integer atomic maxima (order independent) over an array preset to INT_MIN.
+// ---------------------------------------------------------------------------
+constexpr int EQ_NT = 256;
+
+__global__ void __launch_bounds__(EQ_NT)
+k_red_colexp(const RedDesc* __restrict__ descs, const double* __restrict__ X,
+             int* __restrict__ ex) {
+  const RedDesc d = descs[blockIdx.x];
+  const int r0 = blockIdx.y * EQ_ROWS;
+  if (r0 >= d.M) return;
+  const int r1 = min(d.M, r0 + EQ_ROWS), n = d.n, tid = threadIdx.x;
+  __shared__ int sh[NMAX_INST];
+  for (int c = tid; c < n; c += EQ_NT) sh[c] = INT_MIN;
+  __syncthreads();
+  // lane -> (row slot, column): min(n, EQ_NT) columns per pass
+  const int cw = n < EQ_NT ? n : EQ_NT, nrs = EQ_NT / cw;
+  const int cl = tid % cw, rs = tid / cw;
+  const double* __restrict__ x = X + d.w_off;
+  if (rs < nrs)
+    for (int c = cl; c < n; c += cw) {
+      int e = INT_MIN;
+      for (int t = r0 + rs; t < r1; t += nrs) {
+        const double v = fabs(x[(int64_t)t * n + c]);
+        if (v > 0.0 && v <= DBL_MAX) {
+          int q;
+          (void)frexp(v, &q);
+          e = max(e, q);
+        }
+      }
+      if (e != INT_MIN) atomicMax(&sh[c], e);
+    }
+  __syncthreads();
+  for (int c = tid; c < n; c += EQ_NT)
+    if (sh[c] != INT_MIN) atomicMax(&ex[d.tau_off + c], sh[c]);
+}
+
+__global__ void __launch_bounds__(EQ_NT)
+k_red_scale_copy(const RedDesc* __restrict__ descs, const double* __restrict__ X,
+                 const int* __restrict__ ex, double* __restrict__ W) {
+  const RedDesc d = descs[blockIdx.x];
+  const int r0 = blockIdx.y * EQ_ROWS;
+  if (r0 >= d.M) return;
+  const int r1 = min(d.M, r0 + EQ_ROWS), n = d.n;
+  __shared__ int sh[NMAX_INST];
+  for (int c = threadIdx.x; c < n; c += EQ_NT) sh[c] = -col_exp(ex[d.tau_off + c]);
+  __syncthreads();
+  const int64_t base = d.w_off + (int64_t)r0 * n, cnt = (int64_t)(r1 - r0) * n;
+  for (int64_t e = threadIdx.x; e < cnt; e += EQ_NT)
+    W[base + e] = ldexp(X[base + e], sh[(int)(e % n)]);
 }
 
 // ---------------------------------------------------------------------------
@@ -899,10 +966,21 @@ hipError_t launch_red_qinit(const RedDesc* d, int B, double* Q1, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, double* Xr,
-                             hipStream_t s) {
+hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, const int* ex,
+                             double* Xr, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_red_extract, dim3(B), dim3(QNT), 0, s, d, W, Xr);
+  hipLaunchKernelGGL(k_red_extract, dim3(B), dim3(QNT), 0, s, d, W, ex, Xr);
+  return hipGetLastError();
+}
+
+// W = X with its columns equilibrated; ex (sum of n ints) receives the
+// exponents and must hold INT_MIN on entry
+hipError_t launch_red_equilibrate(const RedDesc* d, int B, int maxM, const double* X, int* ex,
+                                  double* W, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  const dim3 grid(B, (maxM + EQ_ROWS - 1) / EQ_ROWS);
+  hipLaunchKernelGGL(k_red_colexp, grid, dim3(EQ_NT), 0, s, d, X, ex);
+  hipLaunchKernelGGL(k_red_scale_copy, grid, dim3(EQ_NT), 0, s, d, X, ex, W);
   return hipGetLastError();
 }
 

@@ -696,3 +696,27 @@ def test_pcg_ne_early_iterates_are_biased_unlike_pcg_aug():
             assert z.max() > 10.0, z
         else:
             assert z.max() < 4.0, z
+
+
+def test_oracle_gls_is_scale_equivariant():
+    """X -> X S (S diagonal: one factor for all columns, 1e-140 or 1e150, or
+    one per column in [1e-120, 1e120]) with R_c -> R_c S maps the GLS
+    estimate to S^-1 beta and leaves u unchanged: the oracle meets this at
+    rounding level far outside the range where squared entries stay finite."""
+    import copy
+    insts = list(synth.small_batch(seed=601, B=3, G_rng=(2, 6), M_rng=(30, 300),
+                                   n_rng=(2, 6), K_rng=(1, 3)))
+    insts += list(synth.small_batch(seed=603, B=2, G_rng=(2, 5), M_rng=(40, 200),
+                                    n_rng=(2, 5), K_rng=(1, 2), constraints=2))
+    rng = np.random.default_rng(5)
+    for inst in insts:
+        b0, U0, _ = gls.sur_solution(inst)
+        for sc in (np.full(inst.n, 1e-140), np.full(inst.n, 1e150),
+                   10.0 ** rng.uniform(-120, 120, inst.n)):
+            si = copy.deepcopy(inst)
+            si.W = si.W * sc
+            if si.Rc is not None:
+                si.Rc = si.Rc * sc
+            b1, U1, _ = gls.sur_solution(si)
+            assert rel_err(b1 * sc[:, None], b0) < 1e-12
+            assert rel_err(U1, U0) < 1e-12
