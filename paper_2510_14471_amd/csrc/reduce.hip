@@ -396,6 +396,121 @@ k_leaf_apply(const RedDesc* __restrict__ descs, int panel, const double* __restr
   }
 }
 
+// ---- leaf apply on the matrix cores ----------------------------------------
+// C_s <- (I - V_s op(T_s) V_s^T) C_s with v_mfma_f64_16x16x4f64 (D = A B + D,
+// A 16 x 4, B 4 x 16).  Lane l = 16 g + j supplies A[j][g] and B[g][j], and
+// holds D[g + 4 r][j] in register r.  Workgroup (instance, 64 target
+// columns, segment of TS rows); wave w owns 16 of the columns and keeps the
+// whole TS x 16 block of C in registers, in the accumulator layout: row
+// tile t, register r -> row 16 t + g + 4 r, column j.  The summation index
+// of each product runs in the order that makes its B operand a register the
+// lane already holds:
+//   Z  = V^T C    (i x c):   k-step (t, r) takes row 16 t + g + 4 r, whose
+//                            value is C's register r of tile t;
+//   Z' = op(T) Z  (i x c):   k-step (it, r) takes i = 16 it + g + 4 r, Z's
+//                            register r of tile it;
+//   C -= V Z'     (row x c): k-step (mt, r) takes i = 16 mt + g + 4 r, Z''s
+//                            register r of tile mt.
+// V sits in LDS with row stride VLD = 36 doubles (the update's operand
+// pattern, 16 rows by 4 consecutive columns, then touches every bank pair
+// exactly twice per wave; the first product's, 4 rows by 16 columns, at most
+// four times); op(T) comes straight from global memory (16 values per lane).
+typedef double md4 __attribute__((ext_vector_type(4)));
+constexpr int VLD = 36;
+constexpr int TT = TS / 16;   // row tiles per segment
+
+__device__ __forceinline__ void stage_v_mf(double (*Vs)[VLD], const double* __restrict__ a0,
+                                           int ld, int rows, int w) {
+  const int tid = threadIdx.x;
+  for (int b = 0; b < TS * RP; b += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = b + q * 256 + tid, r = e / RP, j = e % RP;
+      v[q] = (j < w && r < rows && r > j) ? a0[(int64_t)r * ld + j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = b + q * 256 + tid, r = e / RP, j = e % RP;
+      Vs[r][j] = (j < w && r < rows && r == j) ? 1.0 : v[q];
+    }
+  }
+}
+
+template <int TGT>
+__global__ void __launch_bounds__(256, 2)
+k_leaf_apply_mf(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
+                const double* __restrict__ Tleaf, double* __restrict__ C) {
+  const RedDesc d = descs[blockIdx.x];
+  const int c0 = panel * RP;
+  if (c0 >= d.kr) return;
+  const int w = min(RP, d.kr - c0), rows_all = d.M - c0, sg = blockIdx.z, r0 = sg * TS;
+  if (r0 >= rows_all) return;
+  const ApplyTarget a = apply_target<TGT>(d, c0, w, C);
+  const int col0 = blockIdx.y * 64;
+  if (col0 >= a.ncols) return;
+  const int rs = min(TS, rows_all - r0), ws = min(rs, w);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 15, g = lane >> 4;
+  const int col = col0 + wave * 16 + j;
+  const bool ok = col < a.ncols;
+  __shared__ __align__(16) double Vs[TS][VLD];
+  // C block into registers (all loads in flight before the first use)
+  double* cc = a.cb + (int64_t)r0 * a.ld + col;
+  md4 c[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * t + g + 4 * r;
+      c[t][r] = (ok && row < rs) ? cc[(int64_t)row * a.ld] : 0.0;
+    }
+  stage_v_mf(Vs, W + d.w_off + (int64_t)(c0 + r0) * d.n + c0, d.n, rs, ws);
+  __syncthreads();
+  // Z = V^T C
+  md4 z[2];
+#pragma unroll
+  for (int it = 0; it < 2; ++it) z[it] = md4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < TT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int it = 0; it < 2; ++it)
+        z[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[16 * t + g + 4 * r][16 * it + j],
+                                                     c[t][r], z[it], 0, 0, 0);
+  // Z' = op(T) Z, negated for the update; A[m][k] = op(T)[16 mt + j][16 it + g + 4 r]
+  const double* Tp = Tleaf + d.leaf_off + ((int64_t)panel * d.nseg0 + sg) * RP * RP;
+  md4 zp[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    zp[mt] = md4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = 16 * mt + j, kk = 16 * it + g + 4 * r;
+        const double ta = (TGT == TGT_W) ? Tp[kk * RP + ii] : Tp[ii * RP + kk];
+        zp[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ta, z[it][r], zp[mt], 0, 0, 0);
+      }
+  }
+  // C -= V Z'
+#pragma unroll
+  for (int t = 0; t < TT; ++t)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[16 * t + j][16 * mt + g + 4 * r],
+                                                    zp[mt][r], c[t], 0, 0, 0);
+#pragma unroll
+  for (int t = 0; t < TT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * t + g + 4 * r;
+      if (ok && row < rs) cc[(int64_t)row * a.ld] = c[t][r];
+    }
+}
+
 // Q_t on the segments' first rows: stack row h = 32 s + i is row 256 s + i of
 // the panel (i < ws_s); V_t staged in LDS TS rows at a time, two passes over
 // those target rows (Z = V_t^T C, then C -= V_t op(T_t) Z).
@@ -937,7 +1052,7 @@ hipError_t launch_red_panel(const RedDesc* d, int B, int panel, int maxseg, int 
   hipLaunchKernelGGL(k_tsqr_leaf, dim3(B, maxseg), dim3(256), 0, s, d, panel, W, Tleaf, Stk);
   if (hipError_t e = hipGetLastError()) return e;
   if (maxcols > 0)
-    hipLaunchKernelGGL(k_leaf_apply<TGT_W>, dim3(B, (maxcols + 31) / 32, maxseg), dim3(256), 0,
+    hipLaunchKernelGGL(k_leaf_apply_mf<TGT_W>, dim3(B, (maxcols + 63) / 64, maxseg), dim3(256), 0,
                        s, d, panel, (const double*)W, (const double*)Tleaf, W);
   if (hipError_t e = hipGetLastError()) return e;
   hipLaunchKernelGGL(k_tsqr_tree, dim3(B), dim3(RPNT), 0, s, d, panel, W, Stk, tau, T);
@@ -955,7 +1070,7 @@ hipError_t launch_red_q1_panel(const RedDesc* d, int B, int panel, int maxseg, i
   hipLaunchKernelGGL(k_tree_apply<TGT_Q1>, dim3(B, (maxcols + 31) / 32), dim3(256), 0, s, d,
                      panel, Stk, T, Q1);
   if (hipError_t e = hipGetLastError()) return e;
-  hipLaunchKernelGGL(k_leaf_apply<TGT_Q1>, dim3(B, (maxcols + 31) / 32, maxseg), dim3(256), 0,
+  hipLaunchKernelGGL(k_leaf_apply_mf<TGT_Q1>, dim3(B, (maxcols + 63) / 64, maxseg), dim3(256), 0,
                      s, d, panel, W, Tleaf, Q1);
   return hipGetLastError();
 }
