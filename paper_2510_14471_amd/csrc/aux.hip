@@ -129,45 +129,55 @@ k_outer_check(const InstDesc* __restrict__ insts, const BlockDesc* __restrict__ 
   const int K = in.K, n = in.n, kc = in.kc;
   __shared__ int s_any;
   __shared__ double rr[NT / 64], yy[NT / 64];
+  __shared__ double lo_r[KMAX], lo_y[KMAX];
   if (threadIdx.x == 0) s_any = 0;
-  __syncthreads();
+  if ((int)threadIdx.x < KMAX) lo_r[threadIdx.x] = lo_y[threadIdx.x] = 0.0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // rho0 of every refining rhs
+  for (int e = threadIdx.x; e < n * K; e += NT) {
+    const int c = e / K, k = e - c * K;
+    if (ost[in.rhs0 + k] != ST_ACTIVE) continue;
+    const int64_t bi = in.b_off + e;
+    double v = (h2 ? h2[bi] : 0.0) - xtw_sign * XtW[in.t_off + e];
+    for (int q = 0; q < kc; ++q)
+      v -= Rc[in.rc_off + (int64_t)q * n + c] * wc[in.c_off + (int64_t)q * K + k];
+    rho0[bi] = v;
+  }
+  __syncthreads();
+  // The lower block is measured in the coordinates of the orthonormal
+  // factor: with X_i = Q_i R_i, X_i^T u = h_i is R_i^T (Q_i^T u) = h_i, so its
+  // residual is R_i^-T rho0_i (for h2 = 0: Q^T u), which does not change when
+  // the columns of X are scaled.  One (block, rhs) pair per thread.
+  for (int e = threadIdx.x; e < in.G * K; e += NT) {
+    const int i = e / K, k = e - i * K;
+    if (ost[in.rhs0 + k] != ST_ACTIVE) continue;
+    const BlockDesc bd = blks[in.blk0 + i];
+    const double* Ri = R + bd.r_off;
+    const int ni = bd.ni;
+    const int64_t o = in.b_off + (int64_t)bd.col * K + k;
+    double zr[QR_NMAX], zh[QR_NMAX];
+    double ar = 0.0, ay = 0.0;
+    for (int a = 0; a < ni; ++a) {
+      double sr = rho0[o + (int64_t)a * K];
+      double sh = h2 ? h2[o + (int64_t)a * K] : 0.0;
+      for (int c = 0; c < a; ++c) {
+        sr -= Ri[c * ni + a] * zr[c];
+        sh -= Ri[c * ni + a] * zh[c];
+      }
+      zr[a] = sr / Ri[a * ni + a];
+      zh[a] = sh / Ri[a * ni + a];
+      ar += zr[a] * zr[a];
+      ay += zh[a] * zh[a];
+    }
+    atomicAdd(&lo_r[k], ar);
+    atomicAdd(&lo_y[k], ay);
+  }
+  __syncthreads();
   for (int k = 0; k < K; ++k) {
     const int s_idx = in.rhs0 + k;
     const int o = ost[s_idx];
     if (o != ST_ACTIVE) continue;   // uniform across the workgroup
     double acc_r = 0.0, acc_y = 0.0;
-    for (int c = threadIdx.x; c < n; c += NT) {
-      const int64_t bi = in.b_off + (int64_t)c * K + k;
-      double v = (h2 ? h2[bi] : 0.0) - xtw_sign * XtW[in.t_off + (int64_t)c * K + k];
-      for (int q = 0; q < kc; ++q)
-        v -= Rc[in.rc_off + (int64_t)q * n + c] * wc[in.c_off + (int64_t)q * K + k];
-      rho0[bi] = v;
-    }
-    __syncthreads();
-    // the lower block is measured in the coordinates of the orthonormal
-    // factor: with X_i = Q_i R_i, X_i^T u = h_i is R_i^T (Q_i^T u) = h_i, so
-    // its residual is R_i^-T rho0_i (for h2 = 0: Q^T u), which does not
-    // change when the columns of X are scaled
-    for (int i = threadIdx.x; i < in.G; i += NT) {
-      const BlockDesc bd = blks[in.blk0 + i];
-      const double* Ri = R + bd.r_off;
-      const int ni = bd.ni;
-      const int64_t o = in.b_off + (int64_t)bd.col * K + k;
-      double zr[QR_NMAX], zh[QR_NMAX];
-      for (int a = 0; a < ni; ++a) {
-        double sr = rho0[o + (int64_t)a * K];
-        double sh = h2 ? h2[o + (int64_t)a * K] : 0.0;
-        for (int c = 0; c < a; ++c) {
-          sr -= Ri[c * ni + a] * zr[c];
-          sh -= Ri[c * ni + a] * zh[c];
-        }
-        zr[a] = sr / Ri[a * ni + a];
-        zh[a] = sh / Ri[a * ni + a];
-        acc_r += zr[a] * zr[a];
-        acc_y += zh[a] * zh[a];
-      }
-    }
     for (int q = wv; q < kc; q += NT / 64) {
       double s = 0.0;
       for (int c = lane; c < n; c += 64)
@@ -183,6 +193,8 @@ k_outer_check(const InstDesc* __restrict__ insts, const BlockDesc* __restrict__ 
     // restriction contributions (few rows): one thread
     double extra_r = 0.0, extra_y = 0.0;
     if (threadIdx.x == 0) {
+      extra_r = lo_r[k];
+      extra_y = lo_y[k];
       for (int q = 0; q < kc; ++q) {
         const int64_t ci = in.c_off + (int64_t)q * K + k;
         const double rv = rvec ? rvec[ci] : 0.0;

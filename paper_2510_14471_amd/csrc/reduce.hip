@@ -9,8 +9,9 @@
 // and applied to the trailing columns of W; then the explicit first Mr
 // columns of Q = Q_0 Q_1 ..., Q1 = Q [I; 0] (M x Mr), accumulated backwards.
 //   k_tsqr_leaf, k_tsqr_tree       factor panel p (below)
-//   k_leaf_apply, k_tree_apply     C <- Q_p^T C (trailing columns of W) or
-//                                  C <- Q_p C (Q1)
+//   k_leaf_apply_mf, k_tree_apply_mf   C <- Q_p^T C (trailing columns of W)
+//                                      or C <- Q_p C (Q1), on the FP64
+//                                      matrix cores
 //   k_red_qinit       Q1 <- [I; 0]
 //   k_red_extract     reduced regressors (the rows of R)
 // Solve (per right-hand side block Y, M x G K):
@@ -65,10 +66,10 @@ __device__ __forceinline__ double vpanel(const double* __restrict__ a0, int ld, 
 // tree's V in the stack buffer.
 //   k_tsqr_leaf        factor a segment in registers; V_s, T_s; R_s to the stack
 //   k_tsqr_tree        factor the stack in place; T_t; R into W
-//   k_leaf_apply       C_s <- (I - V_s op(T_s) V_s^T) C_s, one pass over C
-//   k_tree_apply       the same with Q_t on the segments' first rows
+//   k_leaf_apply_mf    C_s <- (I - V_s op(T_s) V_s^T) C_s, one pass over C
+//   k_tree_apply_mf    the same with Q_t on the segments' first rows
 constexpr int TS = RED_LEAF;      // rows per leaf segment
-constexpr int TSJ = TS / 8;       // rows per thread in the leaf kernels (8 row slots)
+constexpr int TSJ = TS / 8;       // rows per thread in the leaf factorization (8 row slots)
 
 // T of a block reflector (forward, columnwise): T[j][j] = tau_j,
 // T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j] with S = V^T V.  Column j needs the
@@ -264,27 +265,6 @@ k_tsqr_tree(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
   }
 }
 
-// Vs[r][j] = V[h0 + r][j] for r < TS (vpanel rows h0.. of a panel block of
-// `rows` rows and w reflector columns at a0, row stride ld), 256 threads with
-// eight loads in flight each
-__device__ __forceinline__ void stage_vpanel(double (*Vs)[RP], const double* __restrict__ a0,
-                                             int ld, int h0, int rows, int w) {
-  const int tid = threadIdx.x;
-  for (int b = 0; b < TS * RP; b += 8 * 256) {
-    double v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = b + q * 256 + tid, r = h0 + e / RP, j = e % RP;
-      v[q] = (j < w && r < rows && r > j) ? a0[(int64_t)r * ld + j] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = b + q * 256 + tid, r = h0 + e / RP, j = e % RP;
-      Vs[e / RP][j] = (j < w && r < rows && r == j) ? 1.0 : v[q];
-    }
-  }
-}
-
 // Target of the applies: the trailing columns of W (TGT_W, op(T) = T^T:
 // Q_p^T) or the columns c0.. of Q1 (TGT_Q1, op(T) = T: Q_p).
 enum : int { TGT_W = 1, TGT_Q1 = 2 };
@@ -307,93 +287,6 @@ __device__ __forceinline__ ApplyTarget apply_target(const RedDesc& d, int c0, in
     a.cb = C + d.q1_off + (int64_t)c0 * d.Mr + c0;
   }
   return a;
-}
-
-// 32 target columns of one segment: thread (row slot, column) holds the
-// column's TSJ rows of the segment in registers; Z = V^T C reduced over the
-// slots, Z' = op(T) Z, C -= V Z', one read and one write of C.  V is staged
-// twice, sharing its LDS with the reduction of Z, so that two workgroups fit
-// a CU (keeping V resident for several column chunks, at one workgroup per
-// CU, was slower).
-template <int TGT>
-__global__ void __launch_bounds__(256, 2)
-k_leaf_apply(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ W,
-             const double* __restrict__ Tleaf, double* __restrict__ C) {
-  const RedDesc d = descs[blockIdx.x];
-  const int c0 = panel * RP;
-  if (c0 >= d.kr) return;
-  const int w = min(RP, d.kr - c0), rows_all = d.M - c0, sg = blockIdx.z, r0 = sg * TS;
-  if (r0 >= rows_all) return;
-  const ApplyTarget a = apply_target<TGT>(d, c0, w, C);
-  const int col0 = blockIdx.y * 32;
-  if (col0 >= a.ncols) return;
-  const int rs = min(TS, rows_all - r0), ws = min(rs, w);
-  const int tid = threadIdx.x, cl = tid & 31, slot = tid >> 5, col = col0 + cl;
-  const bool ok = col < a.ncols;
-  __shared__ __align__(16) double smem[TS * RP];
-  __shared__ double Ts[RP][RP + 1];
-  double (*Vs)[RP] = reinterpret_cast<double (*)[RP]>(smem);
-  double (*red)[RP][32] = reinterpret_cast<double (*)[RP][32]>(smem);
-  double (*Zs)[33] = reinterpret_cast<double (*)[33]>(smem + 4 * RP * 32);
-  double (*Z2s)[33] = reinterpret_cast<double (*)[33]>(smem + 4 * RP * 32 + RP * 33);
-  const double* v0 = W + d.w_off + (int64_t)(c0 + r0) * d.n + c0;
-  stage_vpanel(Vs, v0, d.n, 0, rs, ws);
-  {
-    const double* Tp = Tleaf + d.leaf_off + ((int64_t)panel * d.nseg0 + sg) * RP * RP;
-    for (int e = tid; e < RP * RP; e += 256) {
-      const int i = e / RP, jj = e % RP;
-      Ts[i][jj] = (TGT == TGT_W) ? Tp[jj * RP + i] : Tp[i * RP + jj];
-    }
-  }
-  double* cc = a.cb + (int64_t)r0 * a.ld + col;
-  double x[TSJ];
-#pragma unroll
-  for (int j = 0; j < TSJ; ++j) {
-    const int r = slot + 8 * j;
-    x[j] = (ok && r < rs) ? cc[(int64_t)r * a.ld] : 0.0;
-  }
-  __syncthreads();
-  double z[RP];
-#pragma unroll
-  for (int i = 0; i < RP; ++i) z[i] = 0.0;
-#pragma unroll
-  for (int j = 0; j < TSJ; ++j) {
-    const double* vr = &Vs[slot + 8 * j][0];
-#pragma unroll
-    for (int i = 0; i < RP; ++i) z[i] += vr[i] * x[j];
-  }
-#pragma unroll
-  for (int i = 0; i < RP; ++i) z[i] += __shfl_xor(z[i], 32, 64);
-  const int wave = tid >> 6;
-  __syncthreads();   // every lane is done with Vs
-  if ((tid & 63) < 32)
-#pragma unroll
-    for (int i = 0; i < RP; ++i) red[wave][i][cl] = z[i];
-  __syncthreads();
-  for (int i = slot * 4; i < slot * 4 + 4; ++i)
-    Zs[i][cl] = red[0][i][cl] + red[1][i][cl] + red[2][i][cl] + red[3][i][cl];
-  __syncthreads();
-  for (int i = slot * 4; i < slot * 4 + 4; ++i) {
-    double s2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < RP; ++k) s2 += Ts[i][k] * Zs[k][cl];
-    Z2s[i][cl] = s2;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < RP; ++i) z[i] = Z2s[i][cl];
-  __syncthreads();   // every lane has its Z' column
-  stage_vpanel(Vs, v0, d.n, 0, rs, ws);
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < TSJ; ++j) {
-    const int r = slot + 8 * j;
-    const double* vr = &Vs[r][0];
-    double v = x[j];
-#pragma unroll
-    for (int i = 0; i < RP; ++i) v -= vr[i] * z[i];
-    if (ok && r < rs) cc[(int64_t)r * a.ld] = v;
-  }
 }
 
 // ---- leaf apply on the matrix cores ----------------------------------------
@@ -419,20 +312,22 @@ typedef double md4 __attribute__((ext_vector_type(4)));
 constexpr int VLD = 36;
 constexpr int TT = TS / 16;   // row tiles per segment
 
+// rows h0 .. h0 + TS - 1 of a stored reflector block (unit diagonal and
+// zeros above it implicit) into Vs, with row stride VLD
 __device__ __forceinline__ void stage_v_mf(double (*Vs)[VLD], const double* __restrict__ a0,
-                                           int ld, int rows, int w) {
+                                           int ld, int h0, int rows, int w) {
   const int tid = threadIdx.x;
   for (int b = 0; b < TS * RP; b += 8 * 256) {
     double v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int e = b + q * 256 + tid, r = e / RP, j = e % RP;
+      const int e = b + q * 256 + tid, r = h0 + e / RP, j = e % RP;
       v[q] = (j < w && r < rows && r > j) ? a0[(int64_t)r * ld + j] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int e = b + q * 256 + tid, r = e / RP, j = e % RP;
-      Vs[r][j] = (j < w && r < rows && r == j) ? 1.0 : v[q];
+      const int e = b + q * 256 + tid, r = h0 + e / RP, j = e % RP;
+      Vs[e / RP][j] = (j < w && r < rows && r == j) ? 1.0 : v[q];
     }
   }
 }
@@ -464,7 +359,7 @@ k_leaf_apply_mf(const RedDesc* __restrict__ descs, int panel, const double* __re
       const int row = 16 * t + g + 4 * r;
       c[t][r] = (ok && row < rs) ? cc[(int64_t)row * a.ld] : 0.0;
     }
-  stage_v_mf(Vs, W + d.w_off + (int64_t)(c0 + r0) * d.n + c0, d.n, rs, ws);
+  stage_v_mf(Vs, W + d.w_off + (int64_t)(c0 + r0) * d.n + c0, d.n, 0, rs, ws);
   __syncthreads();
   // Z = V^T C
   md4 z[2];
@@ -511,88 +406,100 @@ k_leaf_apply_mf(const RedDesc* __restrict__ descs, int panel, const double* __re
     }
 }
 
-// Q_t on the segments' first rows: stack row h = 32 s + i is row 256 s + i of
-// the panel (i < ws_s); V_t staged in LDS TS rows at a time, two passes over
-// those target rows (Z = V_t^T C, then C -= V_t op(T_t) Z).
+// Tree apply on the matrix cores, with the lane layout and summation orders
+// of k_leaf_apply_mf.  Workgroup (instance, 64 target columns): the target
+// rows are the segments' first rows (stack row h = 32 s + i is row 256 s + i
+// of the panel, i < ws_s), taken TS stack rows at a time, twice: Z = V_t^T C
+// over all of them, then C -= V_t Z' with Z' = op(T) Z.
 template <int TGT>
 __global__ void __launch_bounds__(256, 2)
-k_tree_apply(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ Stk,
-             const double* __restrict__ T, double* __restrict__ C) {
+k_tree_apply_mf(const RedDesc* __restrict__ descs, int panel, const double* __restrict__ Stk,
+                const double* __restrict__ T, double* __restrict__ C) {
   const RedDesc d = descs[blockIdx.x];
   const int c0 = panel * RP;
   if (c0 >= d.kr) return;
   const int w = min(RP, d.kr - c0), rows_all = d.M - c0;
   const int nseg = (rows_all + TS - 1) / TS, H = nseg * RP;
   const ApplyTarget a = apply_target<TGT>(d, c0, w, C);
-  const int col0 = blockIdx.y * 32;
+  const int col0 = blockIdx.y * 64;
   if (col0 >= a.ncols) return;
-  const int tid = threadIdx.x, cl = tid & 31, slot = tid >> 5, col = col0 + cl;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 15, g = lane >> 4;
+  const int col = col0 + wave * 16 + j;
   const bool ok = col < a.ncols;
   const double* v0 = Stk + d.stk_off + (int64_t)panel * d.nseg0 * RP * RP;
-  __shared__ __align__(16) double smem[TS * RP];   // V chunks, or the reduction of Z
-  __shared__ double Ts[RP][RP + 1];
-  __shared__ double Zs[RP][33];
-  double (*Vs)[RP] = reinterpret_cast<double (*)[RP]>(smem);
-  double (*red)[RP][32] = reinterpret_cast<double (*)[RP][32]>(smem);
-  for (int e = tid; e < RP * RP; e += 256) {
-    const int i = e / RP, j = e % RP;
-    const double* Tp = T + d.t_off + (int64_t)panel * RP * RP;
-    Ts[i][j] = (TGT == TGT_W) ? Tp[j * RP + i] : Tp[i * RP + j];
-  }
-  // target row of stack row h, or -1 for the zero rows of a short last segment
+  __shared__ __align__(16) double Vs[TS][VLD];
+  // target row of stack row h, or -1 (zero rows of a short segment, or past H)
   auto trow = [&](int h) -> int {
-    const int s = h / RP, i = h - s * RP;
-    const int rs = min(TS, rows_all - s * TS);
-    return i < min(rs, w) ? s * TS + i : -1;
+    if (h >= H) return -1;
+    const int sg = h / RP, i = h - sg * RP;
+    const int rs = min(TS, rows_all - sg * TS);
+    return i < min(rs, w) ? sg * TS + i : -1;
   };
-  double z[RP];
+  md4 z[2];
 #pragma unroll
-  for (int i = 0; i < RP; ++i) z[i] = 0.0;
+  for (int it = 0; it < 2; ++it) z[it] = md4{0.0, 0.0, 0.0, 0.0};
   for (int h0 = 0; h0 < H; h0 += TS) {
-    __syncthreads();
-    stage_vpanel(Vs, v0, RP, h0, H, w);
-    __syncthreads();
-    for (int j = 0; j < TSJ; ++j) {
-      const int h = h0 + slot + 8 * j;
-      const int tr = h < H ? trow(h) : -1;
-      const double x = (ok && tr >= 0) ? a.cb[(int64_t)tr * a.ld + col] : 0.0;
-      const double* vr = &Vs[slot + 8 * j][0];
+    md4 c[TT];
 #pragma unroll
-      for (int i = 0; i < RP; ++i) z[i] += vr[i] * x;
-    }
+    for (int t = 0; t < TT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tr = trow(h0 + 16 * t + g + 4 * r);
+        c[t][r] = (ok && tr >= 0) ? a.cb[(int64_t)tr * a.ld + col] : 0.0;
+      }
+    __syncthreads();
+    stage_v_mf(Vs, v0, RP, h0, H, w);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < TT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int it = 0; it < 2; ++it)
+          z[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[16 * t + g + 4 * r][16 * it + j],
+                                                       c[t][r], z[it], 0, 0, 0);
   }
+  const double* Tp = T + d.t_off + (int64_t)panel * RP * RP;
+  md4 zp[2];
 #pragma unroll
-  for (int i = 0; i < RP; ++i) z[i] += __shfl_xor(z[i], 32, 64);
-  const int wave = tid >> 6;
-  __syncthreads();   // every lane is done with the last V chunk
-  if ((tid & 63) < 32)
+  for (int mt = 0; mt < 2; ++mt) {
+    zp[mt] = md4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < RP; ++i) red[wave][i][cl] = z[i];
-  __syncthreads();
-  for (int i = slot * 4; i < slot * 4 + 4; ++i)
-    Zs[i][cl] = red[0][i][cl] + red[1][i][cl] + red[2][i][cl] + red[3][i][cl];
-  __syncthreads();
+    for (int it = 0; it < 2; ++it)
 #pragma unroll
-  for (int i = 0; i < RP; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < RP; ++k) s += Ts[i][k] * Zs[k][cl];
-    z[i] = s;
+      for (int r = 0; r < 4; ++r) {
+        const int ii = 16 * mt + j, kk = 16 * it + g + 4 * r;
+        const double ta = (TGT == TGT_W) ? Tp[kk * RP + ii] : Tp[ii * RP + kk];
+        zp[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ta, z[it][r], zp[mt], 0, 0, 0);
+      }
   }
   for (int h0 = 0; h0 < H; h0 += TS) {
-    __syncthreads();
-    stage_vpanel(Vs, v0, RP, h0, H, w);
-    __syncthreads();
-    for (int j = 0; j < TSJ; ++j) {
-      const int h = h0 + slot + 8 * j;
-      const int tr = h < H ? trow(h) : -1;
-      if (!(ok && tr >= 0)) continue;
-      const double* vr = &Vs[slot + 8 * j][0];
-      double v = a.cb[(int64_t)tr * a.ld + col];
+    md4 c[TT];
 #pragma unroll
-      for (int i = 0; i < RP; ++i) v -= vr[i] * z[i];
-      a.cb[(int64_t)tr * a.ld + col] = v;
-    }
+    for (int t = 0; t < TT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tr = trow(h0 + 16 * t + g + 4 * r);
+        c[t][r] = (ok && tr >= 0) ? a.cb[(int64_t)tr * a.ld + col] : 0.0;
+      }
+    __syncthreads();
+    stage_v_mf(Vs, v0, RP, h0, H, w);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < TT; ++t)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[16 * t + j][16 * mt + g + 4 * r],
+                                                      zp[mt][r], c[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < TT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tr = trow(h0 + 16 * t + g + 4 * r);
+        if (ok && tr >= 0) a.cb[(int64_t)tr * a.ld + col] = c[t][r];
+      }
   }
 }
 
@@ -1058,7 +965,7 @@ hipError_t launch_red_panel(const RedDesc* d, int B, int panel, int maxseg, int 
   hipLaunchKernelGGL(k_tsqr_tree, dim3(B), dim3(RPNT), 0, s, d, panel, W, Stk, tau, T);
   if (hipError_t e = hipGetLastError()) return e;
   if (maxcols > 0)
-    hipLaunchKernelGGL(k_tree_apply<TGT_W>, dim3(B, (maxcols + 31) / 32), dim3(256), 0, s, d,
+    hipLaunchKernelGGL(k_tree_apply_mf<TGT_W>, dim3(B, (maxcols + 63) / 64), dim3(256), 0, s, d,
                        panel, (const double*)Stk, (const double*)T, W);
   return hipGetLastError();
 }
@@ -1067,7 +974,7 @@ hipError_t launch_red_q1_panel(const RedDesc* d, int B, int panel, int maxseg, i
                               const double* W, const double* Tleaf, const double* Stk,
                               const double* T, double* Q1, hipStream_t s) {
   if (B <= 0 || maxseg <= 0 || maxcols <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tree_apply<TGT_Q1>, dim3(B, (maxcols + 31) / 32), dim3(256), 0, s, d,
+  hipLaunchKernelGGL(k_tree_apply_mf<TGT_Q1>, dim3(B, (maxcols + 63) / 64), dim3(256), 0, s, d,
                      panel, Stk, T, Q1);
   if (hipError_t e = hipGetLastError()) return e;
   hipLaunchKernelGGL(k_leaf_apply_mf<TGT_Q1>, dim3(B, (maxcols + 63) / 64, maxseg), dim3(256), 0,
