@@ -16,4 +16,4 @@ Contents
 
 Parity status of every function is stated in its docstring.
 """
-from . import gls, pcg_aug, pcg_ne, grad, reduce  # noqa: F401
+from . import gls, pcg_aug, pcg_ne, grad, reduce, mvrglm  # noqa: F401

@@ -14,6 +14,9 @@ from .sur import (  # noqa: F401
     config4,
     small_batch,
     mc_sur,
+    MVRInstance,
+    var_regressors,
+    mvrglm_var,
     e1_setup,
     e2_setup,
     tiny_integer_sur,

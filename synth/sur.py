@@ -340,6 +340,101 @@ def mc_sur(seed: int = 21, B: int = 256, K: int = 16, G: int = 4, M: int = 20, n
     return SURBatch(out, name=f"mc_sur_s{seed}")
 
 
+# --------------------------------------------------------------------------
+# multivariate model with exclusion restrictions (common regressors)
+# --------------------------------------------------------------------------
+
+@dataclass
+class MVRInstance:
+    """Y = Z0 B + U with exclusions: equation i keeps the columns sel[i] of
+    Z0 (its other coefficients are zero).  Rows of U ~ N(0, Omega)."""
+    Z0: np.ndarray                 # M x N
+    sel: List[np.ndarray]          # per equation, kept column indices (ascending)
+    Omega: np.ndarray              # G x G
+    Y: np.ndarray                  # M x G x K
+    B_true: np.ndarray             # N x G (zeros at the exclusions)
+
+    @property
+    def G(self) -> int:
+        return int(self.Omega.shape[0])
+
+    @property
+    def M(self) -> int:
+        return int(self.Z0.shape[0])
+
+    @property
+    def N(self) -> int:
+        return int(self.Z0.shape[1])
+
+    @property
+    def K(self) -> int:
+        return int(self.Y.shape[2])
+
+    def to_sur(self) -> SURInstance:
+        """The same model as a SUR with X_i = Z0[:, sel_i] (column selection)."""
+        W = np.concatenate([self.Z0[:, s] for s in self.sel], axis=1)
+        beta = np.concatenate([self.B_true[s, i] for i, s in enumerate(self.sel)])
+        return SURInstance(n_i=[int(len(s)) for s in self.sel], W=W, Omega=self.Omega,
+                           Y=self.Y, beta_true=np.repeat(beta[:, None], self.K, axis=1))
+
+
+def var_regressors(rng, M: int, N: int, lags: int = 4, lam_max: float = 0.9,
+                   burn: int = 50) -> np.ndarray:
+    """M x N regressors whose rows follow a VAR(lags) process: random
+    coefficient matrices A_l scaled by s^l, s chosen so that the largest
+    root modulus of the companion matrix is lam_max; N(0, I) innovations."""
+    A = [rng.standard_normal((N, N)) / np.sqrt(N * lags) for _ in range(lags)]
+    comp = np.zeros((N * lags, N * lags))
+    comp[:N, :] = np.concatenate(A, axis=1)
+    comp[N:, :-N] = np.eye(N * (lags - 1))
+    rho = np.abs(np.linalg.eigvals(comp)).max()
+    s = lam_max / rho
+    A = [a * s ** (l + 1) for l, a in enumerate(A)]
+    steps = M + (burn if lam_max < 1.0 else lags)
+    z = np.zeros((steps + lags, N))
+    for t in range(lags, steps + lags):
+        z[t] = sum(A[l] @ z[t - 1 - l] for l in range(lags)) + rng.standard_normal(N)
+    return z[-M:]
+
+
+def _omega_with_condition(rng, G: int, cond: float) -> np.ndarray:
+    V, _ = np.linalg.qr(rng.standard_normal((G, G)))
+    ev = np.geomspace(1.0, cond, G)
+    Om = (V * ev) @ V.T
+    return 0.5 * (Om + Om.T)
+
+
+def mvrglm_var(seed: int = 31, B: int = 6, K: int = 4, G: int = 12, M: int = 300,
+               N: int = 60, sparsity: float = 0.26, lam_max: float = 0.9,
+               omega_cond: float = 4.48) -> List[MVRInstance]:
+    """Restricted multivariate models of the VAR experiments: Z0 (M x N)
+    with VAR(4) rows of largest root lam_max, B (N x G) with a fraction
+    `sparsity` of its entries excluded (zero; every equation keeps at least
+    its first column), Omega with condition number omega_cond.  Each
+    instance draws its own Z0, exclusions and Omega."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(B):
+        Z0 = var_regressors(rng, M, N, lam_max=lam_max)
+        Z0 = Z0 / np.abs(Z0).max()
+        sel = []
+        Btrue = np.zeros((N, G))
+        for i in range(G):
+            keep = rng.random(N) >= sparsity
+            keep[0] = True
+            idx = np.flatnonzero(keep)
+            sel.append(idx)
+            Btrue[idx, i] = rng.standard_normal(idx.size)
+        Om = _omega_with_condition(rng, G, omega_cond)
+        F = np.linalg.cholesky(Om)
+        Y = np.empty((M, G, K))
+        fit = Z0 @ Btrue
+        for k in range(K):
+            Y[:, :, k] = fit + rng.standard_normal((M, G)) @ F.T
+        out.append(MVRInstance(Z0=Z0, sel=sel, Omega=Om, Y=Y, B_true=Btrue))
+    return out
+
+
 CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
 
 

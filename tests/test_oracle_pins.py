@@ -720,3 +720,40 @@ def test_oracle_gls_is_scale_equivariant():
             b1, U1, _ = gls.sur_solution(si)
             assert rel_err(b1 * sc[:, None], b0) < 1e-12
             assert rel_err(U1, U0) < 1e-12
+
+
+def test_mvrglm_sur_form_is_the_restricted_gls_and_reduction_keeps_it():
+    """Exclusion-restricted multivariate model: the SUR with kept columns and
+    the full model with the exclusions as restriction rows give the same
+    estimate; the reduced model (Q0^T Y with R0's kept columns) gives it too;
+    and it differs from equation-wise OLS (the restrictions matter)."""
+    from oracle import mvrglm
+    for lam, sp in ((0.9, 0.26), (1.05, 0.8)):
+        inst = synth.mvrglm_var(seed=33, B=1, K=2, G=4, M=80, N=10, sparsity=sp,
+                                lam_max=lam, omega_cond=50.0)[0]
+        b_sur, U_sur = mvrglm.mvrglm_gls(inst)
+        full = mvrglm.full_restricted_form(inst)
+        b_full, U_full, _ = gls.restricted_gls(full)
+        assert rel_err(mvrglm.kept(inst, b_full), b_sur) < 1e-10
+        assert rel_err(U_full, U_sur) < 1e-10
+        excl = np.ones(inst.G * inst.N, bool)
+        for j, sel in enumerate(inst.sel):
+            excl[j * inst.N + sel] = False
+        assert np.abs(b_full[excl]).max() < 1e-10 * np.abs(b_full).max()
+        b_red, _ = gls.sur_gls(mvrglm.reduced_form(inst))
+        assert rel_err(b_red, b_sur) < 1e-10
+        assert rel_err(mvrglm.equationwise_ols(inst), b_sur) > 1e-6
+
+
+def test_var_regressors_have_the_requested_largest_root():
+    """The generated VAR(4) regressors grow like lam_max^t when the largest
+    root is explosive (1.05: about 1.7e4 over 200 steps, up to transients)
+    and stay bounded when it is stationary (0.9)."""
+    rng = np.random.default_rng(3)
+    z = synth.var_regressors(rng, 400, 6, lam_max=1.05)
+    n1, n2 = np.linalg.norm(z[199]), np.linalg.norm(z[399])
+    # an explosive root 1.05 grows the state by about 1.05^200 = 1.7e4 over
+    # 200 steps (up to the transient), a stationary one would not
+    assert 1e3 < n2 / n1 < 1e6
+    z = synth.var_regressors(np.random.default_rng(4), 400, 6, lam_max=0.9)
+    assert np.linalg.norm(z[399]) / np.linalg.norm(z[199]) < 50.0
