@@ -19,7 +19,9 @@ singular, restricted workload (G = 100, M = 5e4, rank G - 2, 10 restrictions)
 are measured the same way through the model reduction (`configs`).  The
 comparator PCG-NE (CG on the normal equations) is timed on the headline
 workload (`pcg_ne`), and the Monte Carlo comparison of the two estimators
-runs at 4096 replications (`montecarlo`).
+runs at 4096 replications (`montecarlo`).  The restricted VAR workload
+(multivariate models with exclusions, common regressors) is timed through
+its own reduction (`mvrglm`).
 
 Prints one JSON line.
 """
@@ -229,6 +231,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_configs:
         out["configs"] = other_configs(glm, torch, synth, args)
+    if not args.no_configs:
+        out["mvrglm"] = mvrglm_config(glm, torch, synth, args)
     if not args.no_ne:
         out["pcg_ne"] = ne_comparator(glm, torch, synth, args)
         out["montecarlo"] = montecarlo(glm, torch, synth)
@@ -285,6 +289,80 @@ def other_configs(glm, torch, synth, args):
         out[name] = entry
         del runner, d
         torch.cuda.empty_cache()
+    return out
+
+
+MVR_MODELS = [(0.9, 0.26, 4.48), (1.05, 0.26, 4.48), (0.9, 0.26, 448.0), (1.05, 0.26, 448.0),
+              (0.9, 0.80, 448.0), (1.05, 0.80, 448.0)]
+
+
+def mvrglm_config(glm, torch, synth, args, per_model=40, K=16):
+    """The restricted VAR workload: 240 multivariate models with exclusions
+    (the six kinds of the paper's VAR experiments, 40 of each: G = 12,
+    M = 300, N = 60, K = 16 right-hand sides), one step = factor + solve.
+    Through the common-regressor reduction (one QR of Z0, N + 1 rows) and,
+    for comparison, through the SUR reduction of X = [Z0[:, sel_i]]; PCG
+    iterations with D = alpha I and with D = diag(omega_ii) (x) I; the error
+    against the oracle on one instance of each kind."""
+    import numpy as np
+    from oracle import mvrglm as omvr
+    insts = []
+    for q, (lam, sp, oc) in enumerate(MVR_MODELS):
+        insts += synth.mvrglm_var(seed=700 + q, B=per_model, K=K, lam_max=lam, sparsity=sp,
+                                  omega_cond=oc)
+    lay, d = glm.pack_mvr(insts)
+    n_solves = lay.n_rhs
+    out = {"workload": f"mvrglm_var4_batch{len(insts)}_K{K}: G=12, M=300, N=60, sparsity "
+                       "26%/80%, largest root 0.90/1.05, cond(Omega) 4.48/448",
+           "instances": len(insts), "solves_per_step": n_solves}
+
+    def timed(make, factor_args, solve_args, steps):
+        s = make()
+        res = None
+        for it in range(steps + 1):
+            if it == 1:
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+            s.factor(*factor_args)
+            res = s.solve(*solve_args)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        st = s.stats()
+        s.close()
+        return dt, res, st
+
+    sample = [q * per_model for q in range(len(MVR_MODELS))]
+    for prec in ("mixed", "fp64"):
+        for precond in ("scalar", "equation"):
+            dt, res, st = timed(lambda: glm.MVRSolver(lay, d["N"], d["sel"], prec,
+                                                      precond=precond),
+                                (d["Z0"],), (d["Omega"], d["y"], None, 1e-12), args.steps)
+            e = {"solves_per_s": round(n_solves / dt, 1), "ms_per_step": round(1000 * dt, 2),
+                 "pcg_iterations": int(st["pcg_iterations"]),
+                 "max_iterations": int(st["max_iterations"])}
+            if precond == "scalar":
+                betas = glm.unpack(lay, res[0], "beta")
+                errs = []
+                for b in sample:
+                    inst = insts[b]
+                    ref = (omvr.mvrglm_gls(inst)[0] if np.linalg.cond(inst.Z0) < 1e3
+                           else omvr.mvrglm_gls_whitened(inst)[0])
+                    errs.append(rel(betas[b], ref))
+                e["max_rel_err_beta"] = {f"lam{m[0]}_sp{m[1]}_om{m[2]}": v
+                                         for m, v in zip(MVR_MODELS, errs)}
+            out[f"{prec}_{'D1' if precond == 'scalar' else 'D2'}"] = e
+            log(f"mvrglm {prec} {precond}: {e['ms_per_step']} ms/step, "
+                f"{e['pcg_iterations']} PCG iterations")
+    surs = [i.to_sur() for i in insts]
+    lay2, d2 = glm.pack_instances(surs)
+    dt, _, st = timed(lambda: glm.SURSolver(lay2, "mixed", reduce=True), (d2["X"], d2["Rc"]),
+                      (d2["Omega"], d2["y"], d2["r"], 1e-12), args.steps)
+    out["mixed_via_sur_reduction"] = {"solves_per_s": round(n_solves / dt, 1),
+                                      "ms_per_step": round(1000 * dt, 2),
+                                      "pcg_iterations": int(st["pcg_iterations"])}
+    log(f"mvrglm via the SUR reduction: {1000 * dt:.1f} ms/step")
+    del d, d2
+    torch.cuda.empty_cache()
     return out
 
 

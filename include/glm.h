@@ -197,6 +197,40 @@ int glm_qr_factor(const glm_shape* shape, glm_precision prec,
 int glm_qr_factor_static(const glm_shape* shape, glm_precision prec, const double* X,
                          const double* Rc, hipStream_t stream, glm_factor** out);
 
+/* Multivariate models with exclusion restrictions (section on multivariate
+ * linear models with parameter restrictions, eq. MvGLM): Y = Z0 B + U with
+ * common regressors Z0 (M_b x N_b, full column rank) and exclusions
+ * b_ic = 0; equation i keeps the columns sel_i of Z0.  This is the SUR with
+ * X_i = Z0[:, sel_i], factored without forming X: one QR of Z0 = Q0 R0
+ * (the model reduction of that section), Q1 = Q0 [I; 0] with
+ * Mr = min(M, N + 1) columns, and the reduced regressors R0[:, sel_i]
+ * factored block by block (which plays the part of the QRDs of [R0; C_i]
+ * for exclusion restrictions).  The handle behaves as a GLM_REDUCED handle
+ * for glm_gls_solve, glm_gls_solve_ne, glm_get_stats and the kernel timers:
+ * beta holds the kept coefficients (n_b = sum of |sel_i| rows, equation by
+ * equation), u is the full model's.  glm_gls_backward and glm_copy_factors
+ * return GLM_EUNSUPPORTED.
+ *
+ *   shape   as for glm_qr_factor, with n_{b,i} = |sel_i| (1 <= n_{b,i} <= N_b)
+ *           and k_b extra restriction rows over the kept coefficients
+ *   prec    GLM_FP64 or GLM_MIXED, optionally | GLM_PRECOND_EQ (GLM_REDUCED
+ *           is implied)
+ *   Z0      device, M_b x N_b per instance, row-major, concatenated; must
+ *           stay valid while the handle is used (u reads it)
+ *   N       host [B], columns of Z0 (N_b <= 2048)
+ *   sel     host, for every equation of every instance (instance-major) its
+ *           n_{b,i} kept column indices, strictly increasing, in [0, N_b)
+ *   Rc      device, k_b x n_b per restricted instance, or NULL
+ *   ws      device workspace of glm_workspace_bytes_common(shape, prec, N,
+ *           sel) bytes
+ * GLM_OK, GLM_EINVAL (bad shape or selection), GLM_EWORKSPACE, GLM_EHIP or
+ * GLM_EUNSUPPORTED (as glm_validate_shape, or N_b > 2048). */
+size_t glm_workspace_bytes_common(const glm_shape* shape, glm_precision prec,
+                                  const int32_t* N, const int32_t* sel);
+int glm_qr_factor_common(const glm_shape* shape, glm_precision prec, const double* Z0,
+                         const int32_t* N, const int32_t* sel, const double* Rc, void* ws,
+                         size_t ws_bytes, hipStream_t stream, glm_factor** out);
+
 /* Solves every (instance, rhs) of the batch with PCG-Aug (projected form:
  * the iteration carries g_i = Pi r_i and one OLS projection per step).
  *

@@ -19,6 +19,7 @@ The GLS solves are oracle.gls (closed forms on dense numpy/scipy algebra).
 Parity status: pinned by tests/test_oracle_pins.py (the SUR form agrees with
 the restricted GLS of the full multivariate model, whose exclusions are
 explicit restriction rows; the reduced model gives the same estimate; the
+whitened least-squares route agrees on well-conditioned regressors; the
 restricted estimate differs from equation-wise OLS).
 """
 from __future__ import annotations
@@ -39,6 +40,28 @@ def sur_form(inst):
 def mvrglm_gls(inst):
     """(beta of the kept coefficients, equation-major, n x K; U, M x G x K)."""
     return gls.sur_gls(sur_form(inst))
+
+
+def mvrglm_gls_whitened(inst):
+    """The same estimate by least squares on the whitened model: with
+    Omega = L L^T, (L^-1 (x) I_M) y = (L^-1 (x) I_M) X beta + white noise, solved
+    by numpy's SVD least squares, whose error grows like cond(X) rather than
+    cond(X)^2 (for regressors too ill-conditioned for the normal equations).
+    Returns (beta n x K, U M x G x K) with U = (Y - fitted) Omega^-1."""
+    sur = sur_form(inst)
+    G, M, K = inst.G, inst.M, inst.K
+    L = np.linalg.cholesky(inst.Omega)
+    Li = sla.solve_triangular(L, np.eye(G), lower=True)
+    X = sla.block_diag(*[sur.X(i) for i in range(G)])          # (G M) x n, equation-major rows
+    Xw = np.kron(Li, np.eye(M)) @ X
+    beta = np.empty((sur.n, K))
+    for k in range(K):
+        yw = (inst.Y[:, :, k] @ Li.T).T.reshape(-1)
+        beta[:, k] = np.linalg.lstsq(Xw, yw, rcond=None)[0]
+    E = inst.Y - gls.fitted(sur, beta)
+    Oinv = Li.T @ Li
+    U = np.einsum("tik,ij->tjk", E, Oinv)
+    return beta, U
 
 
 def full_restricted_form(inst):

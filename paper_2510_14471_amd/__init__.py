@@ -9,4 +9,6 @@ from ._lib import (  # noqa: F401
     glm_gls_backward, glm_gls_solve, glm_profile_enable, glm_profile_read,
     glm_qr_factor, glm_strerror, glm_validate_shape, glm_workspace_bytes,
 )
-from .solver import BatchLayout, SURSolver, gls, pack_instances, unpack  # noqa: F401
+from .solver import (  # noqa: F401
+    BatchLayout, MVRSolver, SURSolver, gls, pack_instances, pack_mvr, unpack,
+)

@@ -11,6 +11,8 @@ import ctypes
 import os
 from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libglm_hip.so")
 
@@ -66,6 +68,11 @@ def _load():
     lib.glm_qr_factor.restype = c_int
     lib.glm_qr_factor_static.argtypes = [POINTER(GlmShape), c_int, P, P, P, POINTER(c_void_p)]
     lib.glm_qr_factor_static.restype = c_int
+    lib.glm_workspace_bytes_common.argtypes = [POINTER(GlmShape), c_int, P, P]
+    lib.glm_workspace_bytes_common.restype = c_size_t
+    lib.glm_qr_factor_common.argtypes = [POINTER(GlmShape), c_int, P, P, P, P, P, c_size_t, P,
+                                         POINTER(c_void_p)]
+    lib.glm_qr_factor_common.restype = c_int
     lib.glm_gls_solve.argtypes = [P, P, P, P, c_double, c_int32, P, P, P, P, P, P]
     lib.glm_gls_solve.restype = c_int
     lib.glm_gls_solve_ne.argtypes = [P, P, P, c_double, c_int32, P, P, P, P]
@@ -93,7 +100,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["glm_validate_shape", "glm_workspace_bytes", "glm_qr_factor",
-            "glm_qr_factor_static", "glm_gls_solve", "glm_gls_solve_ne",
+            "glm_qr_factor_static", "glm_workspace_bytes_common", "glm_qr_factor_common",
+            "glm_gls_solve", "glm_gls_solve_ne",
             "glm_gls_backward", "glm_copy_factors", "glm_plan_passes", "glm_get_stats",
             "glm_profile_enable", "glm_profile_read", "glm_factor_destroy", "glm_strerror"]
 
@@ -163,6 +171,30 @@ def glm_qr_factor_static(shape: Shape, precision: int, X, Rc, stream=None) -> c_
     rc = _lib.glm_qr_factor_static(shape.ptr(), int(precision), _dp(X), _dp(Rc),
                                    _stream(stream), ctypes.byref(h))
     _check(rc, "glm_qr_factor_static")
+    return h
+
+
+def _host_i32(values):
+    """A host int32 array for a pointer argument (kept alive by the caller)."""
+    arr = np.ascontiguousarray(np.asarray(values, dtype=np.int32))
+    return arr, arr.ctypes.data_as(c_void_p)
+
+
+def glm_workspace_bytes_common(shape: Shape, precision: int, N, sel) -> int:
+    a_n, p_n = _host_i32(N)
+    a_s, p_s = _host_i32(sel)
+    return int(_lib.glm_workspace_bytes_common(shape.ptr(), int(precision), p_n, p_s))
+
+
+def glm_qr_factor_common(shape: Shape, precision: int, Z0, N, sel, Rc, ws,
+                         stream=None) -> c_void_p:
+    a_n, p_n = _host_i32(N)
+    a_s, p_s = _host_i32(sel)
+    h = c_void_p()
+    rc = _lib.glm_qr_factor_common(shape.ptr(), int(precision), _dp(Z0), p_n, p_s, _dp(Rc),
+                                   _dp(ws), ws.numel() * ws.element_size(), _stream(stream),
+                                   ctypes.byref(h))
+    _check(rc, "glm_qr_factor_common")
     return h
 
 

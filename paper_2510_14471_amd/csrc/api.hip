@@ -516,6 +516,10 @@ struct RedPlan {
   // output tiles of Q1^T Y (t1) and of Q1 D (t2), grouped by XCD
   std::vector<GemmTile> t1, t2;
   std::vector<int32_t> G, M, K, k, n;
+  // common regressors: W is Z0 (N_b columns) and the reduced regressors of
+  // equation i are the columns sel of R (sum of n_i entries per instance)
+  bool common = false;
+  std::vector<int32_t> sel;
   glm_shape sub{};
   int64_t sumMn = 0, sumMGK = 0, sumMrn = 0, sumMrGK = 0, sumn = 0, sumT = 0, sumG2 = 0,
           sumZp = 0, sumMMr = 0, sumnK = 0, sumLeaf = 0;
@@ -523,7 +527,7 @@ struct RedPlan {
   size_t o_desc = 0, o_W = 0, o_tau = 0, o_T = 0, o_Tleaf = 0, o_Stk = 0, o_Q1 = 0, o_Xr = 0,
          o_yr = 0, o_ur = 0,
          o_dd = 0, o_Og = 0, o_Ow = 0, o_sing = 0, o_t1 = 0, o_t2 = 0, o_Zp = 0, o_lb = 0,
-         o_cexp = 0, o_sub = 0, sub_bytes = 0, total = 0;
+         o_cexp = 0, o_sel = 0, o_sub = 0, sub_bytes = 0, total = 0;
 };
 
 // Tile table of a batched product: every instance's output tiles (rows x
@@ -555,11 +559,17 @@ std::vector<GemmTile> xcd_tiles(const std::vector<RedDesc>& dd, bool out_rows_fu
   return out;
 }
 
-int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
+// wcols (host [B], or null): common regressors Z0 with wcols[b] columns,
+// equation i keeping the columns sel (host, sum of n_i entries per instance,
+// strictly increasing within an equation, each below wcols[b])
+int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r,
+                  const int32_t* wcols = nullptr, const int32_t* sel = nullptr) {
   int rc = validate(s);
   if (rc != GLM_OK) return rc;
+  if (wcols && !sel) return GLM_EINVAL;
   r = RedPlan();
   r.B = s->batch;
+  r.common = wcols != nullptr;
   int64_t noff = 0, rhs = 0, om = 0;
   for (int b = 0; b < r.B; ++b) {
     RedDesc d{};
@@ -567,8 +577,24 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     d.G = s->G[b];
     d.K = s->K[b];
     d.inst = b;
-    int n = 0;
-    for (int i = 0; i < d.G; ++i) n += s->n[noff + i];
+    int nsub = 0;
+    for (int i = 0; i < d.G; ++i) nsub += s->n[noff + i];
+    d.nsub = nsub;
+    int n = nsub;
+    if (wcols) {
+      n = wcols[b];
+      if (n < 1 || n > NMAX_INST) return n < 1 ? GLM_EINVAL : GLM_EUNSUPPORTED;
+      d.sel_off = (int)r.sel.size();
+      for (int i = 0; i < d.G; ++i) {
+        const int ni = s->n[noff + i];
+        if (ni > n) return GLM_EINVAL;
+        for (int c = 0; c < ni; ++c) {
+          const int v = sel[r.sel.size()];
+          if (v < 0 || v >= n || (c > 0 && v <= r.sel.back())) return GLM_EINVAL;
+          r.sel.push_back(v);
+        }
+      }
+    }
     d.n = n;
     d.Mr = std::min(d.M, n + 1);
     d.kr = std::min(d.M, n);
@@ -598,9 +624,9 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
     r.maxMr = std::max(r.maxMr, d.Mr);
     r.sumMn += (int64_t)d.M * n;
     r.sumMMr += (int64_t)d.M * d.Mr;
-    r.sumnK += (int64_t)n * d.K;
+    r.sumnK += (int64_t)nsub * d.K;
     r.sumMGK += (int64_t)d.M * P;
-    r.sumMrn += (int64_t)d.Mr * n;
+    r.sumMrn += (int64_t)d.Mr * nsub;
     r.sumMrGK += (int64_t)d.Mr * P;
     r.sumn += n;
     r.sumT += (int64_t)npan * RED_PANEL * RED_PANEL;
@@ -646,6 +672,7 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r) {
   r.o_W = take(8 * r.sumMn);
   r.o_tau = take(8 * r.sumn);
   r.o_cexp = take(4 * r.sumn);
+  r.o_sel = take(4 * r.sel.size());
   r.o_T = take(8 * r.sumT);
   r.o_Tleaf = take(8 * r.sumLeaf);
   r.o_Stk = take(8 * r.sumLeaf);
@@ -1250,10 +1277,11 @@ int factor_entry(const glm_shape* shape, glm_precision prec, const double* X,
 
 int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
                    const double* Rc, void* ws, size_t ws_bytes, hipStream_t stream,
-                   glm_factor** out, bool pinned) {
+                   glm_factor** out, bool pinned, const int32_t* wcols = nullptr,
+                   const int32_t* sel = nullptr) {
   glm_factor* f = new (std::nothrow) glm_factor();
   if (!f) return GLM_EINVAL;
-  int rc = make_red_plan(shape, base, f->rp);
+  int rc = make_red_plan(shape, base, f->rp, wcols, sel);
   if (rc != GLM_OK) {
     delete f;
     return rc;
@@ -1288,6 +1316,9 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
   if (!e)
     e = hipMemcpyAsync(f->ws + r.o_t2, r.t2.data(), sizeof(GemmTile) * r.t2.size(),
                        hipMemcpyHostToDevice, stream);
+  if (!e && r.common)
+    e = hipMemcpyAsync(f->ws + r.o_sel, r.sel.data(), 4 * r.sel.size(), hipMemcpyHostToDevice,
+                       stream);
   // W = X with power-of-two column scaling (undone in the extracted R rows)
   if (!e) e = launch_fill<int>(f->at<int>(r.o_cexp), r.sumn, INT_MIN, stream);
   if (!e) e = launch_red_equilibrate(dd, r.B, r.maxM, X, f->at<int>(r.o_cexp), W, stream);
@@ -1300,7 +1331,10 @@ int factor_reduced(const glm_shape* shape, glm_precision base, const double* X,
   for (int p = r.maxpan - 1; p >= 0 && !e; --p)
     e = launch_red_q1_panel(dd, r.B, p, r.maxseg, r.maxMr - p * RED_PANEL, W, Tleaf, Stk, T, Q1,
                             stream);
-  if (!e) e = launch_red_extract(dd, r.B, W, f->at<int>(r.o_cexp), f->at<double>(r.o_Xr), stream);
+  if (!e)
+    e = launch_red_extract(dd, r.B, W, f->at<int>(r.o_cexp),
+                           r.common ? f->at<int>(r.o_sel) : nullptr, f->at<double>(r.o_Xr),
+                           stream);
   if (e != hipSuccess) {
     delete f;
     return GLM_EHIP;
@@ -1325,7 +1359,8 @@ int red_full_u(glm_factor* f, const double* Omega, const double* Y, const double
   int* sing = f->at<int>(rp.o_sing);
   GLM_CHECK(launch_red_ginv(dd, rp.B, Omega, f->at<double>(rp.o_Ow), f->at<double>(rp.o_Og),
                             sing, s));
-  GLM_CHECK(launch_red_u(dd, rp.B, rp.maxM, f->sub->d_inst(), f->sub->d_blk(), f->X, b, Y,
+  GLM_CHECK(launch_red_u(dd, rp.B, rp.maxM, f->sub->d_inst(), f->sub->d_blk(),
+                         rp.common ? f->at<int>(rp.o_sel) : nullptr, f->X, b, Y,
                          f->at<double>(rp.o_Og), U, s));
   std::vector<int> hs(rp.B, 0);
   GLM_CHECK(hipMemcpyAsync(hs.data(), sing, 4 * (size_t)rp.B, hipMemcpyDeviceToHost, s));
@@ -1407,6 +1442,24 @@ int glm_qr_factor(const glm_shape* shape, glm_precision prec, const double* X,
                   const double* Rc, void* ws, size_t ws_bytes, hipStream_t stream,
                   glm_factor** out) {
   return factor_entry(shape, prec, X, Rc, ws, ws_bytes, stream, out, true);
+}
+
+size_t glm_workspace_bytes_common(const glm_shape* shape, glm_precision prec,
+                                  const int32_t* N, const int32_t* sel) {
+  if (!prec_ok(prec) || !N || !sel) return 0;
+  const glm_precision base = (glm_precision)((int)prec & ~GLM_REDUCED);
+  RedPlan r;
+  if (make_red_plan(shape, base, r, N, sel) != GLM_OK) return 0;
+  return r.total;
+}
+
+int glm_qr_factor_common(const glm_shape* shape, glm_precision prec, const double* Z0,
+                         const int32_t* N, const int32_t* sel, const double* Rc, void* ws,
+                         size_t ws_bytes, hipStream_t stream, glm_factor** out) {
+  if (!shape || !Z0 || !N || !sel || !out || !prec_ok(prec)) return GLM_EINVAL;
+  *out = nullptr;
+  const glm_precision base = (glm_precision)((int)prec & ~GLM_REDUCED);
+  return factor_reduced(shape, base, Z0, Rc, ws, ws_bytes, stream, out, true, N, sel);
 }
 
 int glm_qr_factor_static(const glm_shape* shape, glm_precision prec, const double* X,
@@ -1544,6 +1597,7 @@ int glm_gls_backward(glm_factor* f, const double* Omega, const double* beta, con
                      hipStream_t stream) {
   if (!f || !Omega || !beta || !u || !g_beta || !dy) return GLM_EINVAL;
   if (!(tol >= 0.0)) return GLM_EINVAL;
+  if (f->reduced && f->rp.common) return GLM_EUNSUPPORTED;
   if (f->reduced)
     return backward_reduced(f, Omega, beta, u, g_beta, g_u, tol, max_iter, dy, dOmega, dX,
                             info, iters, stream);

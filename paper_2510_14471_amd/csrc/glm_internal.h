@@ -37,7 +37,7 @@ struct InstDesc {
   int64_t q_off;   // Q / X (M x n)
   int64_t v_off;   // vectors (M x G x K)
   int64_t om_off;  // Omega (G x G)
-  int64_t b_off;   // beta-like (n x K)
+  int64_t b_off;   // beta-like (nsub x K)
   int64_t t_off;   // reduced projections ((n + kc) x K)
   int64_t col_off; // column -> block map (n)
   int64_t c_off;   // restriction vectors (kc x K)
@@ -98,14 +98,17 @@ struct RedDesc {
   int rhs0;        // first (instance, rhs) index
   int inst;        // batch index of the instance
   int nseg0;       // row segments of the first panel's TSQR (ceil(M / 256))
-  int pad;
+  int nsub;        // columns of the reduced regressors (sum of n_i); n (the
+                   // columns of W) is equal except for common regressors
+  int sel_off;     // common regressors: first entry of the instance's column
+                   // selection (sum of n_i entries); otherwise 0
   int64_t leaf_off;  // T factors of the TSQR leaves (panels x nseg0 x 32 x 32)
   int64_t stk_off;   // stacked R factors / tree reflectors (panels x nseg0 x 32 x 32)
   int64_t w_off;   // W copy: reflectors and R (M x n, row-major); also X and dX
   int64_t q1_off;  // Q1 = Q [I; 0] (M x Mr)
-  int64_t b_off;   // beta-like (n x K)
+  int64_t b_off;   // beta-like (nsub x K)
   int64_t v_off;   // full vectors (M x G x K)
-  int64_t xr_off;  // reduced regressors (Mr x n)
+  int64_t xr_off;  // reduced regressors (Mr x nsub)
   int64_t vr_off;  // reduced vectors (Mr x G x K)
   int64_t tau_off; // reflector scalars (n)
   int64_t t_off;   // block-reflector factors T (panels x 32 x 32)
@@ -240,7 +243,7 @@ hipError_t launch_red_q1_panel(const RedDesc* d, int B, int panel, int maxseg, i
                               const double* T, double* Q1, hipStream_t s);
 hipError_t launch_red_qinit(const RedDesc* d, int B, double* Q1, hipStream_t s);
 hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, const int* ex,
-                             double* Xr, hipStream_t s);
+                             const int* sel, double* Xr, hipStream_t s);
 hipError_t launch_red_equilibrate(const RedDesc* d, int B, int maxM, const double* X, int* ex,
                                   double* W, hipStream_t s);
 hipError_t launch_red_gemm_tn(const RedDesc* d, const GemmTile* tiles, int ntiles,
@@ -248,7 +251,8 @@ hipError_t launch_red_gemm_tn(const RedDesc* d, const GemmTile* tiles, int ntile
 hipError_t launch_red_ginv(const RedDesc* d, int B, const double* Om, double* A, double* Og,
                           int* sing, hipStream_t s);
 hipError_t launch_red_u(const RedDesc* d, int B, int maxM, const InstDesc* sinst,
-                       const BlockDesc* sblk, const double* X, const double* beta,
+                       const BlockDesc* sblk, const int* sel, const double* X,
+                       const double* beta,
                        const double* Y, const double* Og, double* U, hipStream_t s);
 hipError_t launch_red_singular(const RedDesc* d, int B, int chunks, const GemmTile* tiles2,
                               int ntiles2, const int* sing, const double* Om, const double* Og,

@@ -92,7 +92,7 @@ __device__ void form_t(const double (*S)[RP + 1], const double* tau, int w, doub
   }
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W,
             double* __restrict__ Tleaf, double* __restrict__ Stk) {
   const RedDesc d = descs[blockIdx.x];
@@ -105,7 +105,7 @@ k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
   const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
   const bool colok = c < w;
   __shared__ double red[32][4];
-  __shared__ double dsum[32], pivrow[32], tau_s[32], par[3];
+  __shared__ double dsum[32], pivrow[2][32], tau_s[32], par[3];
   __shared__ double S[RP][RP + 1];
   __shared__ double part[4][RP][RP];
   double a[TSJ];
@@ -116,19 +116,21 @@ k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
   }
   if (tid < 32) tau_s[tid] = 0.0;
   // Householder in registers, the arithmetic of qr32_factor (reflector p:
-  // v = [1; x scale], H = I - tau v v^T, a_k -= tau v (pivrow_k + scale dsum_k))
-  for (int p = 0; p < ws; ++p) {
-    double dot = 0.0;
+  // v = [1; x scale], H = I - tau v v^T, a_k -= tau v (pivrow_k + scale dsum_k));
+  // the sweep that applies reflector p also forms the pivot row and the dot
+  // products of reflector p + 1
+  double dot = 0.0;
 #pragma unroll
-    for (int j = 0; j < TSJ; ++j) {
-      const int r = slot + 8 * j;
-      const double ap = shfl_col(a[j], p);
-      if (r == p && colok) pivrow[c] = a[j];
-      if (r > p && r < rs && c >= p) dot += ap * a[j];
-    }
+  for (int j = 0; j < TSJ; ++j) {
+    const int r = slot + 8 * j;
+    const double ap = shfl_col(a[j], 0);
+    if (r == 0 && colok) pivrow[0][c] = a[j];
+    if (r > 0 && r < rs) dot += ap * a[j];
+  }
+  for (int p = 0; p < ws; ++p) {
     col_sum<256>(dot, p, w, red, dsum);
     if (tid == 0) {
-      const double alpha = pivrow[p];
+      const double alpha = pivrow[p & 1][p];
       const double xnorm2 = dsum[p];
       double beta, tau, scale;
       if (!(xnorm2 > kQrTinyNorm2)) {
@@ -148,7 +150,9 @@ k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
     }
     __syncthreads();
     const double beta = par[0], tau = par[1], scale = par[2];
-    const double wkc = (c > p && colok) ? pivrow[c] + scale * dsum[c] : 0.0;
+    const double wkc = (c > p && colok) ? pivrow[p & 1][c] + scale * dsum[c] : 0.0;
+    const int q = p + 1;
+    dot = 0.0;
 #pragma unroll
     for (int j = 0; j < TSJ; ++j) {
       const int r = slot + 8 * j;
@@ -158,8 +162,11 @@ k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
         if (c > p) a[j] -= tau * vv * wkc;
         if (c == p) a[j] = (r == p) ? beta : vv;
       }
+      const double aq = shfl_col(a[j], q & 31);
+      if (r == q && colok) pivrow[q & 1][c] = a[j];
+      if (r > q && r < rs && c >= q) dot += aq * a[j];
     }
-    __syncthreads();   // pivrow, par and wk are rewritten by the next reflector
+    __syncthreads();   // par and dsum are rewritten by the next reflector
   }
   // reflectors below the diagonal, R_s on and above it
 #pragma unroll
@@ -175,23 +182,28 @@ k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
     const int r = slot + 8 * j;
     if (r < RP) stk[r * RP + c] = (r < ws && colok && c >= r) ? a[j] : 0.0;
   }
-  // S = V^T V (V with the unit diagonal, ws columns)
-  double acc[RP];
-#pragma unroll
-  for (int i = 0; i < RP; ++i) acc[i] = 0.0;
+  // S = V^T V (V with the unit diagonal, ws columns), eight rows of S at a
+  // time to keep the accumulators few
 #pragma unroll
   for (int j = 0; j < TSJ; ++j) {
     const int r = slot + 8 * j;
-    const double v = (c < ws && r < rs) ? (r > c ? a[j] : (r == c ? 1.0 : 0.0)) : 0.0;
-#pragma unroll
-    for (int i = 0; i < RP; ++i) acc[i] += shfl_col(v, i) * v;
+    a[j] = (c < ws && r < rs) ? (r > c ? a[j] : (r == c ? 1.0 : 0.0)) : 0.0;
   }
-#pragma unroll
-  for (int i = 0; i < RP; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
   const int wave = tid >> 6;
-  if ((tid & 63) < 32)
+  for (int i0 = 0; i0 < RP; i0 += 8) {
+    double acc[8];
 #pragma unroll
-    for (int i = 0; i < RP; ++i) part[wave][i][c] = acc[i];
+    for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < TSJ; ++j)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] += shfl_col(a[j], i0 + i) * a[j];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
+    if ((tid & 63) < 32)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) part[wave][i0 + i][c] = acc[i];
+  }
   __syncthreads();
   for (int e = tid; e < RP * RP; e += 256) {
     const int i = e / RP, jj = e % RP;
@@ -516,15 +528,20 @@ k_red_qinit(const RedDesc* __restrict__ descs, double* __restrict__ Q1) {
 }
 
 // Reduced regressors Xr[t][c] = R[t][c] (c >= t, t < kr; zero elsewhere).
+// With common regressors (sel non-null) column c of the reduced regressors
+// is column sel[c] of R (the equation's kept column of Z0).
 __global__ void __launch_bounds__(QNT)
 k_red_extract(const RedDesc* __restrict__ descs, const double* __restrict__ W,
-              const int* __restrict__ ex, double* __restrict__ Xr) {
+              const int* __restrict__ ex, const int* __restrict__ sel,
+              double* __restrict__ Xr) {
   const RedDesc d = descs[blockIdx.x];
-  const int64_t cnt = (int64_t)d.Mr * d.n;
+  const int64_t cnt = (int64_t)d.Mr * d.nsub;
   for (int64_t e = threadIdx.x; e < cnt; e += QNT) {
-    const int t = (int)(e / d.n), c = (int)(e % d.n);
-    Xr[d.xr_off + e] =
-        (t < d.kr && c >= t) ? ldexp(W[d.w_off + e], col_exp(ex[d.tau_off + c])) : 0.0;
+    const int t = (int)(e / d.nsub), cs = (int)(e % d.nsub);
+    const int c = sel ? sel[d.sel_off + cs] : cs;
+    Xr[d.xr_off + e] = (t < d.kr && c >= t)
+                           ? ldexp(W[d.w_off + (int64_t)t * d.n + c], col_exp(ex[d.tau_off + c]))
+                           : 0.0;
   }
 }
 
@@ -792,7 +809,8 @@ __device__ __forceinline__ void stage_rows(double* __restrict__ dst,
 
 __global__ void __launch_bounds__(QNT)
 k_red_u(const RedDesc* __restrict__ descs, const InstDesc* __restrict__ sinst,
-        const BlockDesc* __restrict__ sblk, const double* __restrict__ X,
+        const BlockDesc* __restrict__ sblk, const int* __restrict__ sel,
+        const double* __restrict__ X,
         const double* __restrict__ beta, const double* __restrict__ Y,
         const double* __restrict__ Og, double* __restrict__ U) {
   const RedDesc d = descs[blockIdx.x];
@@ -828,6 +846,7 @@ k_red_u(const RedDesc* __restrict__ descs, const InstDesc* __restrict__ sinst,
     for (int pq = tid; pq < P; pq += QNT) {
       const int g = pq / K, k = pq - g * K, col = s_col[g], ni = s_ni[g];
       const double* br = bb + (int64_t)col * K + k;
+      const int* xs = sel ? sel + d.sel_off + col : nullptr;   // X column of coefficient c
       double acc[8];
 #pragma unroll
       for (int tt = 0; tt < 8; ++tt) acc[tt] = 0.0;
@@ -840,7 +859,7 @@ k_red_u(const RedDesc* __restrict__ descs, const InstDesc* __restrict__ sinst,
           if (c0 + q >= ni) break;
 #pragma unroll
           for (int tt = 0; tt < 8; ++tt)
-            if (tt < nr) acc[tt] += Xs[tt * n + col + c0 + q] * bv[q];
+            if (tt < nr) acc[tt] += Xs[tt * n + (xs ? xs[c0 + q] : col + c0 + q)] * bv[q];
         }
       }
 #pragma unroll
@@ -989,9 +1008,9 @@ hipError_t launch_red_qinit(const RedDesc* d, int B, double* Q1, hipStream_t s) 
 }
 
 hipError_t launch_red_extract(const RedDesc* d, int B, const double* W, const int* ex,
-                             double* Xr, hipStream_t s) {
+                             const int* sel, double* Xr, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_red_extract, dim3(B), dim3(QNT), 0, s, d, W, ex, Xr);
+  hipLaunchKernelGGL(k_red_extract, dim3(B), dim3(QNT), 0, s, d, W, ex, sel, Xr);
   return hipGetLastError();
 }
 
@@ -1021,11 +1040,12 @@ hipError_t launch_red_ginv(const RedDesc* d, int B, const double* Om, double* A,
 }
 
 hipError_t launch_red_u(const RedDesc* d, int B, int maxM, const InstDesc* sinst,
-                       const BlockDesc* sblk, const double* X, const double* beta,
-                       const double* Y, const double* Og, double* U, hipStream_t s) {
+                       const BlockDesc* sblk, const int* sel, const double* X,
+                       const double* beta, const double* Y, const double* Og, double* U,
+                       hipStream_t s) {
   if (B <= 0 || maxM <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_red_u, dim3(B, (maxM + URC - 1) / URC), dim3(QNT), 0, s, d, sinst, sblk,
-                     X, beta, Y, Og, U);
+                     sel, X, beta, Y, Og, U);
   return hipGetLastError();
 }
 

@@ -102,8 +102,31 @@ def unpack(lay: BatchLayout, flat, kind: str):
     return out
 
 
+def pack_mvr(instances, device="cuda:0"):
+    """Uploads multivariate instances with exclusions (Z0, kept columns
+    `sel`, Omega, Y).  Returns (layout, dict with Z0, Omega, y, Rc=None,
+    r=None, N (host list), sel (host flat list)); the layout's n_i are the
+    numbers of kept columns, so beta comes back as the kept coefficients."""
+    lay = BatchLayout([i.G for i in instances], [i.M for i in instances],
+                      [i.K for i in instances], [0] * len(instances),
+                      [[int(len(s)) for s in i.sel] for i in instances])
+    dev = torch.device(device)
+    f64 = torch.float64
+    N = [int(i.N) for i in instances]
+    off_Z = np.cumsum([0] + [i.M * i.N for i in instances]).tolist()
+    Z0 = torch.empty(off_Z[-1], dtype=f64, device=dev)
+    Om = torch.empty(lay.off_Om[-1], dtype=f64, device=dev)
+    y = torch.empty(lay.off_y[-1], dtype=f64, device=dev)
+    for b, inst in enumerate(instances):
+        _put(Z0, off_Z[b], inst.Z0)
+        _put(Om, lay.off_Om[b], inst.Omega)
+        _put(y, lay.off_y[b], inst.Y)
+    sel = [int(v) for inst in instances for s in inst.sel for v in s]
+    return lay, {"Z0": Z0, "Omega": Om, "y": y, "Rc": None, "r": None, "N": N, "sel": sel}
+
+
 # kernel ids of glm_profile_read: the iteration launches of projection passes
-# A and B, and (reduced solvers) the block-reflector applications
+# A and B, and (reduced solvers) the reduced responses Q1^T Y
 PROFILED_KERNELS = (0, 1, 2)
 
 
@@ -114,8 +137,7 @@ class SURSolver:
                  reduce: bool = False, precond: str = "scalar"):
         """reduce: solve through the SUR model reduction (one QR of
         W = [X_1 ... X_G] per instance; the iteration runs on min(M, n + 1)
-        rotated observations).  Forward solves only: backward() and factors()
-        raise on such a solver.
+        rotated observations).  factors() raises on such a solver.
         precond: "scalar" (D = alpha I, alpha = max_i omega_ii) or "equation"
         (D = diag(omega_ii) (x) I_M, one scalar per equation)."""
         if precond not in ("scalar", "equation"):
@@ -268,3 +290,45 @@ class _GLSFunction(torch.autograd.Function):
 def gls(solver: SURSolver, X, Omega, y, tol: float = 1e-12, max_iter: int = 0):
     """Differentiable batched SUR GLS: returns packed (beta, u)."""
     return _GLSFunction.apply(solver, tol, max_iter, X, Omega, y)
+
+
+class MVRSolver(SURSolver):
+    """Multivariate models with exclusion restrictions (common regressors
+    Z0, equation i keeping the columns sel_i): one QR of Z0 per instance and
+    the solve on min(M, N + 1) rotated rows.  Solve and solve_ne as on a
+    reduced SURSolver; no backward() or factors()."""
+
+    def __init__(self, layout: BatchLayout, N, sel, precision: str = "fp64",
+                 device="cuda:0", precond: str = "scalar"):
+        if precond not in ("scalar", "equation"):
+            raise ValueError(precond)
+        self.layout = layout
+        self.reduce = True
+        self.precision = (_lib.PRECISIONS[precision]
+                          | (_lib.GLM_PRECOND_EQ if precond == "equation" else 0))
+        self.device = torch.device(device)
+        self._shape = layout.shape()
+        self._N = list(N)
+        self._sel = list(sel)
+        nbytes = _lib.glm_workspace_bytes_common(self._shape, self.precision, self._N,
+                                                 self._sel)
+        if nbytes == 0:
+            raise _lib.GLMError("shape or column selection rejected")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = None
+        self._X = None
+        self._Rc = None
+        self._profile = False
+        self._prof_acc = {kid: [0, 0.0, 0.0] for kid in PROFILED_KERNELS}
+
+    def factor(self, Z0, Rc=None, stream=None):
+        if self.handle is not None:
+            self._harvest_profile()
+            _lib.glm_factor_destroy(self.handle)
+            self.handle = None
+        self._X, self._Rc = Z0, Rc
+        self.handle = _lib.glm_qr_factor_common(self._shape, self.precision, Z0, self._N,
+                                                self._sel, Rc, self.workspace, stream)
+        if self._profile:
+            _lib.glm_profile_enable(self.handle, True)
+        return self

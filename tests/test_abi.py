@@ -175,3 +175,19 @@ def test_pass_configuration_of_each_parity_case(name):
             assert pass_cases.matches(got["fp32_passes"], want32), (prec, got)
         else:
             assert got["fp32_passes"]["rowvec"] == -1, got
+
+
+def test_common_regressor_workspace_validates_the_selection():
+    """glm_workspace_bytes_common (host only) accepts strictly increasing
+    kept columns below N and rejects anything else with 0."""
+    from paper_2510_14471_amd import _lib
+    shape = _lib.Shape([2], [50], [1], [3, 2])
+    N = [5]
+    assert _lib.glm_workspace_bytes_common(shape, _lib.GLM_FP64, N, [0, 2, 4, 1, 3]) > 0
+    for bad in ([0, 2, 5, 1, 3],      # column past N
+                [0, 2, 2, 1, 3],      # repeated column
+                [2, 0, 4, 1, 3],      # not increasing
+                [0, 2, 4, -1, 3]):
+        assert _lib.glm_workspace_bytes_common(shape, _lib.GLM_FP64, N, bad) == 0, bad
+    wide = _lib.Shape([1], [50], [1], [6])
+    assert _lib.glm_workspace_bytes_common(wide, _lib.GLM_FP64, [5], list(range(6))) == 0

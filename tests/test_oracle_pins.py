@@ -742,6 +742,9 @@ def test_mvrglm_sur_form_is_the_restricted_gls_and_reduction_keeps_it():
         assert np.abs(b_full[excl]).max() < 1e-10 * np.abs(b_full).max()
         b_red, _ = gls.sur_gls(mvrglm.reduced_form(inst))
         assert rel_err(b_red, b_sur) < 1e-10
+        if lam < 1.0:
+            b_w, U_w = mvrglm.mvrglm_gls_whitened(inst)
+            assert rel_err(b_w, b_sur) < 1e-10 and rel_err(U_w, U_sur) < 1e-10
         assert rel_err(mvrglm.equationwise_ols(inst), b_sur) > 1e-6
 
 
