@@ -43,8 +43,12 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE, WRITE_SIZE, calibrated against a plain copy kernel); valid only
 # for the kernel sources it was taken from
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_proj_sur_batch512_k16.json")
-KERNEL_SOURCES = ["paper_2510_14471_amd/csrc/proj.hip",
-                  "paper_2510_14471_amd/csrc/glm_internal.h"]
+# the pass kernels' source and the descriptor structs they read (the text of
+# glm_internal.h from `struct InstDesc` to the pass constants); launcher
+# declarations elsewhere in that header do not change the kernels
+KERNEL_SOURCES = [("paper_2510_14471_amd/csrc/proj.hip", None, None),
+                  ("paper_2510_14471_amd/csrc/glm_internal.h", "struct InstDesc",
+                   "constexpr int PROJ_NT")]
 PASS_NAMES = {0: "k_proj_a<float> (pass A: u <- g + mu u, B = U Omega, d = u.B, T += Q^T B)",
               1: "k_proj_b<float> (pass B: g -= (lambda/alpha)(B - Q T), w -= lambda u, c = g.g)",
               2: "k_red_gemm_tn (model reduction: reduced responses Y_red = Q1^T Y, "
@@ -455,9 +459,13 @@ def montecarlo(glm, torch, synth, iters=(1, 2, 3, 4, 6, 8, 12, 16, 20)):
 def kernel_sources_sha256():
     import hashlib
     h = hashlib.sha256()
-    for rel_path in KERNEL_SOURCES:
+    for rel_path, start, end in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel_path), "rb") as f:
-            h.update(f.read())
+            text = f.read()
+        if start is not None:
+            i = text.index(start.encode())
+            text = text[i:text.index(end.encode(), i)]
+        h.update(text)
     return h.hexdigest()
 
 

@@ -596,6 +596,11 @@ int make_red_plan(const glm_shape* s, glm_precision base, RedPlan& r,
       }
     }
     d.n = n;
+    {
+      // one row of X and Y must fit the full-model u kernel's LDS
+      const int rowlds = RED_U_LDS - (d.G <= 32 ? d.G * d.G : 0);
+      if (n + d.G * d.K > rowlds) return GLM_EUNSUPPORTED;
+    }
     d.Mr = std::min(d.M, n + 1);
     d.kr = std::min(d.M, n);
     d.rhs0 = (int)rhs;

@@ -10,6 +10,10 @@ constexpr int NT = 256;          // threads per workgroup of the tile kernels
 constexpr int KMAX = 16;         // right-hand sides per instance
 constexpr int QR_NMAX = 64;      // widest block the QR kernel factors
 constexpr int NMAX_INST = 8 * NT; // widest instance (n = sum of n_i) of any path
+// doubles of LDS of the full-model u kernel: Omega^g when G <= 32, then one or
+// more rows of X (n) and Y (G K); the reduction plans reject shapes whose row
+// does not fit
+constexpr int RED_U_LDS = 5120;
 
 // Per-(instance, rhs) iteration status.
 enum : int {

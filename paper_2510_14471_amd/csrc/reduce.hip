@@ -92,7 +92,7 @@ __device__ void form_t(const double (*S)[RP + 1], const double* tau, int w, doub
   }
 }
 
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(256, 3)
 k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W,
             double* __restrict__ Tleaf, double* __restrict__ Stk) {
   const RedDesc d = descs[blockIdx.x];
@@ -613,7 +613,15 @@ k_red_scale_copy(const RedDesc* __restrict__ descs, const double* __restrict__ X
 constexpr int GT = 64;
 constexpr int GKC = 16;
 
-// Y_red = Q1^T Y: output Mr x P (P = G K), reduction over the M rows.
+// Y_red = Q1^T Y: output Mr x P (P = G K), reduction over the M rows, on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64, lane l = 16 g + j supplying
+// A[j][g] and B[g][j] and holding D[g + 4 r][j]): wave w owns output rows
+// 16 w .. 16 w + 15 of the tile and its four 16-column blocks; k-step s of a
+// chunk takes rows 4 s + g.  The chunks sit in LDS with row stride GTL = 80
+// doubles, so that the four rows of one operand read touch every bank pair
+// twice.
+constexpr int GTL = GT + 16;
+
 __global__ void __launch_bounds__(256)
 k_red_gemm_tn(const RedDesc* __restrict__ descs, const GemmTile* __restrict__ tiles,
               const double* __restrict__ Q1, const double* __restrict__ Y,
@@ -622,9 +630,9 @@ k_red_gemm_tn(const RedDesc* __restrict__ descs, const GemmTile* __restrict__ ti
   if (tl.inst < 0) return;
   const RedDesc d = descs[tl.inst];
   const int M = d.M, Mr = d.Mr, P = d.G * d.K;
-  __shared__ __align__(16) double As[2][GKC][GT];
-  __shared__ __align__(16) double Bs[2][GKC][GT];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  __shared__ __align__(16) double As[2][GKC][GTL];
+  __shared__ __align__(16) double Bs[2][GKC][GTL];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 15, g = lane >> 4;
   const double* __restrict__ qb = Q1 + d.q1_off;
   const double* __restrict__ yb = Y + d.v_off;
   double ra[4], rb[4];
@@ -632,9 +640,9 @@ k_red_gemm_tn(const RedDesc* __restrict__ descs, const GemmTile* __restrict__ ti
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q, kk = e >> 6, cc = e & 63, t = t0 + kk;
-      const int i = tl.i0 + cc, j = tl.j0 + cc;
+      const int i = tl.i0 + cc, jj = tl.j0 + cc;
       ra[q] = (t < M && i < Mr) ? qb[(int64_t)t * Mr + i] : 0.0;
-      rb[q] = (t < M && j < P) ? yb[(int64_t)t * P + j] : 0.0;
+      rb[q] = (t < M && jj < P) ? yb[(int64_t)t * P + jj] : 0.0;
     }
   };
   auto store = [&](int buf) {
@@ -645,11 +653,9 @@ k_red_gemm_tn(const RedDesc* __restrict__ descs, const GemmTile* __restrict__ ti
       Bs[buf][kk][cc] = rb[q];
     }
   };
-  double acc[4][4];
+  md4 acc[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+  for (int c = 0; c < 4; ++c) acc[c] = md4{0.0, 0.0, 0.0, 0.0};
   const int nk = (M + GKC - 1) / GKC;
   load(0);
   store(0);
@@ -657,30 +663,25 @@ k_red_gemm_tn(const RedDesc* __restrict__ descs, const GemmTile* __restrict__ ti
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
     if (kc + 1 < nk) load((kc + 1) * GKC);
-#pragma unroll 4
-    for (int k = 0; k < GKC; ++k) {
-      const double2 a01 = *reinterpret_cast<const double2*>(&As[buf][k][ty * 4]);
-      const double2 a23 = *reinterpret_cast<const double2*>(&As[buf][k][ty * 4 + 2]);
-      const double2 b01 = *reinterpret_cast<const double2*>(&Bs[buf][k][tx * 4]);
-      const double2 b23 = *reinterpret_cast<const double2*>(&Bs[buf][k][tx * 4 + 2]);
-      const double av[4] = {a01.x, a01.y, a23.x, a23.y};
-      const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+    for (int st = 0; st < GKC / 4; ++st) {
+      const double a = As[buf][4 * st + g][16 * wave + j];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+      for (int c = 0; c < 4; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[buf][4 * st + g][16 * c + j], acc[c],
+                                                      0, 0, 0);
     }
     if (kc + 1 < nk) store(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int i = tl.i0 + ty * 4 + r;
+    const int i = tl.i0 + 16 * wave + g + 4 * r;
     if (i >= Mr) continue;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int j = tl.j0 + tx * 4 + c;
-      if (j < P) Yr[d.vr_off + (int64_t)i * P + j] = acc[r][c];
+      const int jj = tl.j0 + 16 * c + j;
+      if (jj < P) Yr[d.vr_off + (int64_t)i * P + jj] = acc[c][r];
     }
   }
 }
@@ -779,14 +780,14 @@ k_red_ginv(const RedDesc* __restrict__ descs, const double* __restrict__ Om,
 
 // U = (Y - [X_i beta_i]) Omega^g.  Workgroup (instance, URC rows), taken in
 // sub-chunks of ur rows whose X and Y rows are staged in LDS with coalesced
-// loads; Omega^g sits in the same 64 KB of LDS first when G <= 64.  The
-// shape limits keep one row within the rest: G <= 64 has G K <= 1024 and
-// n <= 2048; G > 64 has n + G K <= 1024 + 4096.  Y may be null (zero).  The
+// loads; Omega^g sits in the same 40 KB of LDS first when G <= 32.  The
+// plan guarantees that one row fits the rest (n + G K <= ULDS - G^2 when
+// Omega^g is staged, else n + G K <= ULDS).  Y may be null (zero).  The
 // blocks' columns come from the reduced problem's block table (the same
 // blocks).
 constexpr int RTR = 32;
 constexpr int URC = 64;
-constexpr int ULDS = 8192;     // doubles of LDS: Omega^g (G <= 64), then X and Y rows
+constexpr int ULDS = RED_U_LDS;
 
 // dst[e] = src[e] (src may be null: zeros) for e < count by the workgroup,
 // eight loads in flight per thread
@@ -826,7 +827,7 @@ k_red_u(const RedDesc* __restrict__ descs, const InstDesc* __restrict__ sinst,
     s_ni[g] = bd[g].ni;
   }
   const double* og = Og + d.om_off;
-  const bool og_lds = G <= 64;
+  const bool og_lds = G <= 32;
   if (og_lds)
     for (int e = tid; e < G * G; e += QNT) sm[e] = og[e];
   const double* ogp = og_lds ? sm : og;
