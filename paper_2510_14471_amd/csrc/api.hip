@@ -270,6 +270,7 @@ int make_plan(const glm_shape* s, glm_precision prec_flags, Plan& p, bool allow3
         in.rs_t[0] = in.rs_t[1];
         in.rsa_t[0] = in.rsa_t[1];
         in.rpar_t[0] = in.rpar_t[1];
+        in.tps_t[0] = in.tps_t[1];
         continue;
       }
       const size_t svp = pi ? sizeof(double) : sizeof(float);
@@ -290,6 +291,7 @@ int make_plan(const glm_shape* s, glm_precision prec_flags, Plan& p, bool allow3
         rs = rs / rpar * rpar;   // whole rows per row group
         in.rs_t[pi] = std::max(rs, 1);
         in.rpar_t[pi] = rpar;
+        in.tps_t[pi] = c.gr < 0 ? mf_partial_slots(gp) : rpar;
         // pass A: two vector slabs and PROJ_NQA Q scalars per thread
         const int rows_va = PROJ_NV * PROJ_NT * c.kv / (2 * P);
         const int rows_qa = PROJ_NQA * PROJ_NT / n;
@@ -300,6 +302,7 @@ int make_plan(const glm_shape* s, glm_precision prec_flags, Plan& p, bool allow3
         in.rs_t[pi] = (int)std::max<size_t>(1, std::min<size_t>(64, kLdsBudget / (per_row * svp)));
         in.rsa_t[pi] = in.rs_t[pi];
         in.rpar_t[pi] = 1;
+        in.tps_t[pi] = 1;
         c.lds = std::max(c.lds, per_row * svp * in.rs_t[pi]);
       }
     }
@@ -336,7 +339,7 @@ int make_plan(const glm_shape* s, glm_precision prec_flags, Plan& p, bool allow3
     int trows = std::max(step, (want + step - 1) / step * step);
     in.tile0 = (int)p.tile.size();
     in.tp_stride = std::max<int64_t>(
-        (int64_t)std::max(in.rpar_t[0], in.rpar_t[1]) * n * in.K, (int64_t)in.G * in.G);
+        (int64_t)std::max(in.tps_t[0], in.tps_t[1]) * n * in.K, (int64_t)in.G * in.G);
     int part = 0;
     for (int r0 = 0; r0 < in.M; r0 += trows) {
       TileDesc td{};

@@ -34,10 +34,12 @@ struct InstDesc {
   int ntiles;
   int rs_t[2];     // rows per LDS-staged sub-tile of the passes (FP32, FP64)
   int rpar_t[2];   // row groups per workgroup of the passes (FP32, FP64)
+  int tps_t[2];    // per-tile partial slots of pass A's Q^T B (FP32, FP64): the
+                   // row groups, or fewer where pass A combines them in-kernel
   int rsa_t[2];    // rows per sub-tile of pass A (FP32, FP64)
   int maxit;       // PCG iteration bound m - n + 1
   int nimax;       // largest n_i of the instance
-  int64_t tp_stride;  // elements per tile partial: max(rpar n K, G G)
+  int64_t tp_stride;  // elements per tile partial: max(tps n K, G G)
   int64_t q_off;   // Q / X (M x n)
   int64_t v_off;   // vectors (M x G x K)
   int64_t om_off;  // Omega (G x G)
@@ -88,6 +90,16 @@ template <typename T>
 __host__ __device__ inline int rpar_of(const InstDesc& in) {
   return in.rpar_t[sizeof(T) == 8];
 }
+template <typename T>
+__host__ __device__ inline int tps_of(const InstDesc& in) {
+  return in.tps_t[sizeof(T) == 8];
+}
+// Matrix-core passes (FP32, sixteen rhs): the partial slots pass A writes per
+// tile for G padded to gp.  gp <= 16: the rows of a wave are summed by lane
+// shuffles, one slot per wave; gp = 32 and 64: one slot per row group (64 / gp;
+// summing the two waves of gp = 32 through LDS cost pass A more time than it
+// saved in partial traffic).
+__host__ __device__ inline int mf_partial_slots(int gp) { return gp <= 16 ? 4 : 64 / gp; }
 
 struct RedChunk {
   int inst, p0;

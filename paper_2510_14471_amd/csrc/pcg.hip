@@ -380,7 +380,7 @@ k_reduce_t(const InstDesc* __restrict__ insts, const TileDesc* __restrict__ tile
   const int pr = ch.p0 + threadIdx.x;
   if (pr >= nk) return;
   const int64_t base = tiles[in.tile0].tp_off;
-  const int slots = use_rpar ? rpar_of<T>(in) : 1;   // row-group partials inside a tile
+  const int slots = use_rpar ? tps_of<T>(in) : 1;    // row-group partials inside a tile
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   const int64_t st4 = in.tp_stride;
   for (int r = 0; r < slots; ++r) {

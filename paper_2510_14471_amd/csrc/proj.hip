@@ -516,8 +516,24 @@ __global__ void __launch_bounds__(PNT) k_proj_a(Args3<T> a) {
       }
     }
   }
-  if (on) {
-    T* tp = a.Tpart + tile.tp_off + (int64_t)r * n * K + (int64_t)col * K + k0;
+  // The tile's partial Q^T B, one slot per row group; on the matrix-core
+  // mapping with gp <= 16 the rows of a wave are summed first by shuffles over
+  // the row bits of the lane index, one slot per wave (mf_partial_slots).
+  int slot = r;
+  bool store = on;
+  if constexpr (MF) {
+    if (mm.small) {
+      for (int sh = mm.Gp; sh < 16; sh <<= 1)
+#pragma unroll
+        for (int c = 0; c < NIM; ++c)
+#pragma unroll
+          for (int v = 0; v < KV; ++v) tacc[c][v] += __shfl_xor(tacc[c][v], sh, 64);
+      slot = mm.rgrp;
+      store = on && mm.tq == 0;
+    }
+  }
+  if (store) {
+    T* tp = a.Tpart + tile.tp_off + (int64_t)slot * n * K + (int64_t)col * K + k0;
 #pragma unroll
     for (int c = 0; c < NIM; ++c)
       if (c < ni) {
