@@ -6,8 +6,10 @@ M ~ U{500..5000}, n_i ~ U{3..20}, K = 16 right-hand sides each; X_i intercept
 + N(0,1), Omega = A A^T + 0.1 I), seeded synthetic data drawn on the host and
 resident in HBM before timing.  One step = the model reduction (QR of
 W = [X_1 ... X_G], Q1^T Y) + the per-block QR of the reduced problem + the
-solve of all 8,192 (instance, rhs) pairs + u of the full model.  `value` is
-the mixed-precision throughput; the FP64 path is timed on the same inputs,
+solve of all 8,192 (instance, rhs) pairs + u of the full model, with the
+preconditioner's D = diag(omega_ii) (x) I_M (the paper's D_2; --precond
+scalar selects D = alpha I).  `value` is the mixed-precision throughput;
+the FP64 path is timed on the same inputs and with the same D,
 both without the reduction too, and every run is checked against the CPU
 oracle on a sample of instances at <= 1e-10 relative error.
 
@@ -68,8 +70,9 @@ def rel(a, b):
 class Runner:
     """Times factor + solve of one packed workload on one solver."""
 
-    def __init__(self, glm, torch, lay, d, tol):
+    def __init__(self, glm, torch, lay, d, tol, precond="scalar"):
         self.glm, self.torch, self.lay, self.d, self.tol = glm, torch, lay, d, tol
+        self.precond = precond
 
     def step(self, s):
         s.factor(self.d["X"], self.d["Rc"])
@@ -78,7 +81,7 @@ class Runner:
 
     def run(self, prec, reduce, steps, warmup, profile):
         torch = self.torch
-        s = self.glm.SURSolver(self.lay, prec, reduce=reduce)
+        s = self.glm.SURSolver(self.lay, prec, reduce=reduce, precond=self.precond)
         for _ in range(warmup):
             self.step(s)
         torch.cuda.synchronize()
@@ -121,6 +124,10 @@ def main():
                     help="skip the runs without the model reduction")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the single large, differentiation and singular workloads")
+    ap.add_argument("--precond", choices=("scalar", "equation"), default="equation",
+                    help="the preconditioner's D: diag(omega_ii) (x) I (equation, the paper's "
+                         "D_2; 7 %% fewer PCG iterations on the batched workload) or alpha I, "
+                         "alpha = max omega_ii (scalar, D_1)")
     ap.add_argument("--no-ne", action="store_true",
                     help="skip the PCG-NE comparator and the Monte Carlo study")
     args = ap.parse_args()
@@ -146,7 +153,7 @@ def main():
     torch.cuda.synchronize()
     n_solves = lay.n_rhs
     log(f"packed: X {d['X'].numel() * 8 / 1e9:.2f} GB, y {d['y'].numel() * 8 / 1e9:.2f} GB")
-    runner = Runner(glm, torch, lay, d, args.tol)
+    runner = Runner(glm, torch, lay, d, args.tol, args.precond)
 
     # the product path (model reduction: one QR of W, the iteration on n + 1
     # rotated rows) and the iteration on all M rows, each in mixed precision
@@ -203,7 +210,9 @@ def main():
                                "n_i~U{3..20}, Omega=AA^T+0.1I; step = model reduction (QR of "
                                "W = [X_1..X_G], Q1^T Y) + per-block QR + solve of all "
                                "(instance, rhs), u of the full model",
-                   "instances": len(insts), "solves_per_step": n_solves, "tol": args.tol},
+                   "instances": len(insts), "solves_per_step": n_solves, "tol": args.tol,
+                   "preconditioner": ("D = alpha I, alpha = max omega_ii" if args.precond == "scalar"
+                                      else "D = diag(omega_ii) (x) I_M")},
         "pcg_iterations_per_s": round(mixed["iters"] / mixed["dt"], 1),
         "outer_steps": round(mixed["outer"] / args.steps, 2),
         "max_rel_err": {p: {"beta": e[0], "u": e[1]} for p, e in errs.items()},
@@ -262,7 +271,7 @@ def other_configs(glm, torch, synth, args):
         t = time.perf_counter()
         beta_o, U_o, SU_o = ogls.sur_solution(inst)
         t_oracle = time.perf_counter() - t
-        runner = Runner(glm, torch, lay, d, args.tol)
+        runner = Runner(glm, torch, lay, d, args.tol, args.precond)
         entry = {"oracle_s": round(t_oracle, 2)}
         for prec in ("mixed", "fp64"):
             r = runner.run(prec, True, 1, 1, profile=True)

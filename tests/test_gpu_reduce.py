@@ -28,12 +28,12 @@ def glmlib():
     return glm
 
 
-def run_reduced(glm, insts, precision, tol=1e-13):
-    print(f"[case] reduced {precision} B={len(insts)} G={[i.G for i in insts][:6]} "
+def run_reduced(glm, insts, precision, tol=1e-13, precond="scalar"):
+    print(f"[case] reduced {precision} {precond} B={len(insts)} G={[i.G for i in insts][:6]} "
           f"M={[i.M for i in insts][:6]} n={[i.n for i in insts][:6]} K={insts[0].K} "
           f"k={[i.kc for i in insts][:6]}", flush=True)
     lay, d = glm.pack_instances(insts)
-    s = glm.SURSolver(lay, precision, reduce=True)
+    s = glm.SURSolver(lay, precision, reduce=True, precond=precond)
     s.factor(d["X"], d["Rc"])
     beta, u, _, info, iters = s.solve(d["Omega"], d["y"], d["r"], tol=tol)
     torch.cuda.synchronize()
@@ -156,15 +156,17 @@ def test_reduced_backward_matches_dense_reference(glmlib, precision):
 
 
 @pytest.mark.timeout(900)
+@pytest.mark.parametrize("precond", ["equation", "scalar"])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_reduced_batched_workload_full_size(glmlib, precision):
+def test_reduced_batched_workload_full_size(glmlib, precision, precond):
     """The batched workload (512 instances x 16 rhs) through the reduction,
-    in the launch configuration the benchmark times: all 8,192 (instance,
-    rhs) pairs against the oracle, normwise and element-wise, and
-    Sigma u + X beta = y, X_i^T u_i = 0 on every instance."""
+    in the launch configurations the benchmark times (D = diag(omega_ii) (x) I
+    by default, D = alpha I): all 8,192 (instance, rhs) pairs against the
+    oracle, normwise and element-wise, and Sigma u + X beta = y,
+    X_i^T u_i = 0 on every instance."""
     from test_gpu_fullsize import identities
     insts, refs = batch512_with_oracle()
-    out = run_reduced(glmlib, insts, precision, tol=1e-12)
+    out = run_reduced(glmlib, insts, precision, tol=1e-12, precond=precond)
     worst = assert_all_pairs(insts, refs, out["beta"], out["u"], out["info"], TOL)
     print(f"[worst] reduced {precision} {worst}", flush=True)
     out["solver"].close()
