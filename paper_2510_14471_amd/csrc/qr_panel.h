@@ -66,7 +66,6 @@ struct Qr32Shared {
   double dsum[32];
   double pivrow[2][32];   // the pivot rows of consecutive reflectors, alternating
   double tau_s[32];
-  double par[3];
 };
 
 template <int NT, int U>
@@ -78,14 +77,16 @@ __device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
   double (*red)[NT / 64] = sh.red;
   double* dsum = sh.dsum;
   double* tau_s = sh.tau_s;
-  double* par = sh.par;
   const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
   const bool colok = c < cols;
+  // Every thread forms each reflector's scalars itself (the same arithmetic
+  // on the same shared values), so the two barriers of col_sum are the only
+  // ones per reflector: the sweep writes the other pivot-row buffer, a row
+  // is loaded and stored by the same half-wave in every sweep, and dsum and
+  // red are rewritten only after the next col_sum's first barrier.
+  double beta_j = 0.0, tau_j = 0.0, scale_j = 0.0;
   for (int p = 0; p <= cols; ++p) {
     const int j = p - 1;
-    const double beta_j = (p > 0) ? par[0] : 0.0;
-    const double tau_j = (p > 0) ? par[1] : 0.0;
-    const double scale_j = (p > 0) ? par[2] : 0.0;
     // v^T a_c of reflector j (v = [1; x scale]) from its pivot row and dot
     // products; each lane forms its own column's
     const double wkc =
@@ -122,29 +123,20 @@ __device__ void qr32_factor(double* __restrict__ a0, int rows, int cols, int ld,
       }
     }
     if (p == cols) break;
-    __syncthreads();  // pivrow visible, all rows written
     col_sum<NT>(dot, p, cols, red, dsum);
-    if (tid == 0) {
-      const double alpha = sh.pivrow[p & 1][p];
-      const double xnorm2 = dsum[p];            // squared norm below the pivot
-      const double nrm2 = alpha * alpha + xnorm2;
-      double beta, tau, scale;
-      if (!(xnorm2 > kQrTinyNorm2)) {
-        beta = alpha;  // H = I (LAPACK: tau = 0 when the subcolumn is zero)
-        tau = 0.0;
-        scale = 0.0;
-      } else {
-        const double nrm = sqrt(nrm2);
-        beta = (alpha >= 0.0) ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      par[0] = beta;
-      par[1] = tau;
-      par[2] = scale;
-      tau_s[p] = tau;
+    const double alpha = sh.pivrow[p & 1][p];
+    const double xnorm2 = dsum[p];            // squared norm below the pivot
+    if (!(xnorm2 > kQrTinyNorm2)) {
+      beta_j = alpha;  // H = I (LAPACK: tau = 0 when the subcolumn is zero)
+      tau_j = 0.0;
+      scale_j = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + xnorm2);
+      beta_j = (alpha >= 0.0) ? -nrm : nrm;
+      tau_j = (beta_j - alpha) / beta_j;
+      scale_j = 1.0 / (alpha - beta_j);
     }
-    __syncthreads();
+    if (tid == 0) tau_s[p] = tau_j;
   }
   __syncthreads();
 }

@@ -105,7 +105,7 @@ k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
   const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
   const bool colok = c < w;
   __shared__ double red[32][4];
-  __shared__ double dsum[32], pivrow[2][32], tau_s[32], par[3];
+  __shared__ double dsum[32], pivrow[2][32], tau_s[32];
   __shared__ double S[RP][RP + 1];
   __shared__ double part[4][RP][RP];
   double a[TSJ];
@@ -127,29 +127,27 @@ k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
     if (r == 0 && colok) pivrow[0][c] = a[j];
     if (r > 0 && r < rs) dot += ap * a[j];
   }
+  // Every thread forms the reflector's scalars itself (the same arithmetic on
+  // the same shared values), so the two barriers of col_sum are the only
+  // ones per reflector: the sweep writes the other pivot-row buffer, and
+  // dsum and red are rewritten only after the next col_sum's first barrier,
+  // which every thread reaches after its reads of this reflector's values.
   for (int p = 0; p < ws; ++p) {
     col_sum<256>(dot, p, w, red, dsum);
-    if (tid == 0) {
-      const double alpha = pivrow[p & 1][p];
-      const double xnorm2 = dsum[p];
-      double beta, tau, scale;
-      if (!(xnorm2 > kQrTinyNorm2)) {
-        beta = alpha;
-        tau = 0.0;
-        scale = 0.0;
-      } else {
-        const double nrm = sqrt(alpha * alpha + xnorm2);
-        beta = (alpha >= 0.0) ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      par[0] = beta;
-      par[1] = tau;
-      par[2] = scale;
-      tau_s[p] = tau;
+    const double alpha = pivrow[p & 1][p];
+    const double xnorm2 = dsum[p];
+    double beta, tau, scale;
+    if (!(xnorm2 > kQrTinyNorm2)) {
+      beta = alpha;
+      tau = 0.0;
+      scale = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + xnorm2);
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
     }
-    __syncthreads();
-    const double beta = par[0], tau = par[1], scale = par[2];
+    if (tid == 0) tau_s[p] = tau;
     const double wkc = (c > p && colok) ? pivrow[p & 1][c] + scale * dsum[c] : 0.0;
     const int q = p + 1;
     dot = 0.0;
@@ -166,8 +164,8 @@ k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
       if (r == q && colok) pivrow[q & 1][c] = a[j];
       if (r > q && r < rs && c >= q) dot += aq * a[j];
     }
-    __syncthreads();   // par and dsum are rewritten by the next reflector
   }
+  __syncthreads();   // pivot rows and tau_s complete
   // reflectors below the diagonal, R_s on and above it
 #pragma unroll
   for (int j = 0; j < TSJ; ++j) {
