@@ -242,6 +242,14 @@ def main():
             out["roofline_other"] = others
     del runner, d
     torch.cuda.empty_cache()
+    ceil = stream_ceiling(glm, torch, insts)
+    if "roofline" in out:
+        rl = out["roofline"]
+        rl["same_mix_ceiling"] = ceil
+        if rl.get("traffic"):
+            touched = rl["traffic"] / (rl["avg_us"] * 1e-6) / 1e9
+            rl["touched_gbs"] = round(touched, 1)
+            rl["touched_frac_of_same_mix_ceiling"] = round(touched / ceil["pass_b"]["gbs"], 3)
     if not args.no_configs:
         out["configs"] = other_configs(glm, torch, synth, args)
     if not args.no_configs:
@@ -461,6 +469,41 @@ def montecarlo(glm, torch, synth, iters=(1, 2, 3, 4, 6, 8, 12, 16, 20)):
     log(f"montecarlo: PCG-Aug max|z| {res['pcg_aug']['max_abs_z']}, "
         f"PCG-NE max|z| {res['pcg_ne']['max_abs_z']}")
     del d
+    torch.cuda.empty_cache()
+    return res
+
+
+def stream_ceiling(glm, torch, insts, reps=20):
+    """Rate of a plain streaming kernel (glm_stream_mix) moving the bytes of
+    the reduced solve's projection passes in their pattern, at the full
+    sizes of the batched workload (every rhs active): FP32 vectors of
+    sum Mr G K elements and Q of sum Mr n (Mr = min(M, n + 1)).  Pass B reads
+    u, g, w and Q and writes g and w in place; pass A (without its partial
+    sums) reads u, g and Q and writes u in place; a copy moves one vector."""
+    V = sum(min(i.M, i.n + 1) * i.G * i.K for i in insts)
+    nq = sum(min(i.M, i.n + 1) * i.n for i in insts)
+    V, nq = (V + 3) // 4 * 4, (nq + 3) // 4 * 4
+    dev = torch.device("cuda")
+    u, g, w = (torch.randn(V, device=dev) for _ in range(3))
+    Q = torch.randn(nq, device=dev)
+    mixes = {"pass_b": ([u, Q], [g, w], [], 5 * V + nq, "read u, g, w, Q; write g, w in place"),
+             "pass_a": ([g, Q], [u], [], 3 * V + nq, "read u, g, Q; write u in place"),
+             "copy": ([u], [], [g], 2 * V, "read one vector, write another")}
+    res = {}
+    for name, (ro, rw, wo, elems, what) in mixes.items():
+        for _ in range(3):
+            glm.glm_stream_mix(ro, rw, wo)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            glm.glm_stream_mix(ro, rw, wo)
+        e1.record()
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        res[name] = {"mix": what, "bytes": 4 * elems, "avg_us": round(us, 2),
+                     "gbs": round(4 * elems / (us * 1e-6) / 1e9, 1)}
+    log("same-mix streaming ceiling: " + ", ".join(f"{k} {v['gbs']} GB/s" for k, v in res.items()))
+    del u, g, w, Q
     torch.cuda.empty_cache()
     return res
 

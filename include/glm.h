@@ -357,6 +357,30 @@ int glm_profile_enable(glm_factor* f, int on);
 int glm_profile_read(glm_factor* f, int kernel_id, int64_t* launches,
                      double* total_ms, double* total_bytes);
 
+/* Measurement aid, not a step of the method: the streaming ceiling of a
+ * read/write mix.  One plain streaming kernel moves the bytes of a
+ * projection pass in the same pattern, with no arithmetic beyond one add per
+ * element, so that the pass's touched bandwidth can be compared with what
+ * the device reaches for that mix (pass B of an iteration reads u, g, w and
+ * Q_i and writes g and w in place; pass A reads u, g and Q_i and writes u in
+ * place and its Q_i^T B_i partial sums).
+ *   ro, ro_len  host arrays of n_ro device pointers (float) and lengths
+ *               (elements): read-only streams;
+ *   rw, rw_len  host array of n_rw device pointers: streams of rw_len
+ *               elements read and then overwritten in place;
+ *   wo, wo_len  host array of n_wo device pointers: write-only streams of
+ *               wo_len elements.
+ * Element e of a written stream becomes 0.5 * (its old value, rw only) +
+ * the sum over read-only streams with ro_len > e of their element e.
+ * Every pointer 16-byte aligned, every length of a given stream positive
+ * and a multiple of 4, at most GLM_STREAM_MAX streams of each kind, no
+ * written stream overlapping another stream; otherwise GLM_EINVAL before
+ * any launch (overlap is not checked).  Enqueued on `stream`; GLM_OK or GLM_EHIP. */
+#define GLM_STREAM_MAX 4
+int glm_stream_mix(const float* const* ro, const int64_t* ro_len, int32_t n_ro,
+                   float* const* rw, int32_t n_rw, int64_t rw_len,
+                   float* const* wo, int32_t n_wo, int64_t wo_len, hipStream_t stream);
+
 void glm_factor_destroy(glm_factor* f);
 
 /* Static description of a return or info code; never NULL. */

@@ -22,6 +22,7 @@ SOURCES = [
     ("aux.hip", "aux.o", []),
     ("reduce.hip", "reduce.o", []),
     ("ne.hip", "ne.o", []),
+    ("stream.hip", "stream.o", []),
     ("api.hip", "api.o", []),
 ]
 ARCH = os.environ.get("GLM_OFFLOAD_ARCH", "gfx950")

@@ -90,6 +90,8 @@ def _load():
     lib.glm_profile_read.argtypes = [P, c_int, POINTER(c_int64), POINTER(c_double),
                                      POINTER(c_double)]
     lib.glm_profile_read.restype = c_int
+    lib.glm_stream_mix.argtypes = [P, P, c_int32, P, c_int32, c_int64, P, c_int32, c_int64, P]
+    lib.glm_stream_mix.restype = c_int
     lib.glm_factor_destroy.argtypes = [P]
     lib.glm_factor_destroy.restype = None
     lib.glm_strerror.argtypes = [c_int]
@@ -103,7 +105,8 @@ EXPORTED = ["glm_validate_shape", "glm_workspace_bytes", "glm_qr_factor",
             "glm_qr_factor_static", "glm_workspace_bytes_common", "glm_qr_factor_common",
             "glm_gls_solve", "glm_gls_solve_ne",
             "glm_gls_backward", "glm_copy_factors", "glm_plan_passes", "glm_get_stats",
-            "glm_profile_enable", "glm_profile_read", "glm_factor_destroy", "glm_strerror"]
+            "glm_profile_enable", "glm_profile_read", "glm_stream_mix", "glm_factor_destroy",
+            "glm_strerror"]
 
 
 def glm_strerror(code: int) -> str:
@@ -264,6 +267,26 @@ def glm_profile_read(h, kernel_id: int):
     _check(_lib.glm_profile_read(h, int(kernel_id), ctypes.byref(n), ctypes.byref(ms),
                                  ctypes.byref(by)), "glm_profile_read")
     return int(n.value), float(ms.value), float(by.value)
+
+
+def glm_stream_mix(ro=(), rw=(), wo=(), stream=None):
+    """Streaming-ceiling kernel: `ro` read-only, `rw` read and overwritten in
+    place (all of one length), `wo` write-only (all of one length); float32
+    device tensors."""
+    for t in (*ro, *rw, *wo):
+        if t.dtype.itemsize != 4:
+            raise GLMError("glm_stream_mix takes float32 tensors")
+    rw_len = {t.numel() for t in rw}
+    wo_len = {t.numel() for t in wo}
+    if len(rw_len) > 1 or len(wo_len) > 1:
+        raise GLMError("glm_stream_mix: read-write and write-only streams each of one length")
+    ro_p = (c_void_p * max(1, len(ro)))(*[_dp(t).value for t in ro])
+    ro_n = (c_int64 * max(1, len(ro)))(*[t.numel() for t in ro])
+    rw_p = (c_void_p * max(1, len(rw)))(*[_dp(t).value for t in rw])
+    wo_p = (c_void_p * max(1, len(wo)))(*[_dp(t).value for t in wo])
+    _check(_lib.glm_stream_mix(ro_p, ro_n, len(ro), rw_p, len(rw), rw_len.pop() if rw else 0,
+                               wo_p, len(wo), wo_len.pop() if wo else 0, _stream(stream)),
+           "glm_stream_mix")
 
 
 def glm_factor_destroy(h):
