@@ -92,6 +92,114 @@ __device__ void form_t(const double (*S)[RP + 1], const double* tau, int w, doub
   }
 }
 
+// Householder QR of a rows x w block (w <= 32) held in registers: thread
+// (slot, c) = (tid / 32, tid % 32) holds column c of rows slot + SL j, j < TJ
+// (SL = NT / 32 row slots), zero for rows past the block and columns past w.
+// Reflector p: v = [1; x scale], H = I - tau v v^T, a_k -= tau v (pivrow_k +
+// scale dsum_k); the sweep that applies reflector p also forms the pivot row
+// and the dot products of reflector p + 1.  Every thread forms the
+// reflector's scalars itself (the same arithmetic on the same shared values),
+// so the two barriers of col_sum are the only ones per reflector: the sweep
+// writes the other pivot-row buffer, and dsum and red are rewritten only
+// after the next col_sum's first barrier, which every thread reaches after
+// its reads of this reflector's values.  On return the registers hold R on
+// and above the diagonal and the reflectors below it (LAPACK geqr2
+// convention), tau_s the reflector scalars.  Called by every thread.
+template <int NT, int TJ>
+__device__ __forceinline__ void qr_regs(double (&a)[TJ], int rows, int w,
+                                        double (*red)[NT / 64], double* dsum,
+                                        double (*pivrow)[32], double* tau_s) {
+  constexpr int SL = NT / 32;
+  const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
+  const bool colok = c < w;
+  const int ws = min(rows, w);
+  if (tid < 32) tau_s[tid] = 0.0;
+  double dot = 0.0;
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) {
+    const int r = slot + SL * j;
+    const double ap = shfl_col(a[j], 0);
+    if (r == 0 && colok) pivrow[0][c] = a[j];
+    if (r > 0 && r < rows) dot += ap * a[j];
+  }
+  for (int p = 0; p < ws; ++p) {
+    col_sum<NT>(dot, p, w, red, dsum);
+    const double alpha = pivrow[p & 1][p];
+    const double xnorm2 = dsum[p];
+    double beta, tau, scale;
+    if (!(xnorm2 > kQrTinyNorm2)) {
+      beta = alpha;
+      tau = 0.0;
+      scale = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + xnorm2);
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    if (tid == 0) tau_s[p] = tau;
+    const double wkc = (c > p && colok) ? pivrow[p & 1][c] + scale * dsum[c] : 0.0;
+    const int q = p + 1;
+    dot = 0.0;
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      const int r = slot + SL * j;
+      const double ap = shfl_col(a[j], p);
+      if (r >= p && r < rows) {
+        const double vv = (r > p) ? ap * scale : 1.0;
+        if (c > p) a[j] -= tau * vv * wkc;
+        if (c == p) a[j] = (r == p) ? beta : vv;
+      }
+      const double aq = shfl_col(a[j], q & 31);
+      if (r == q && colok) pivrow[q & 1][c] = a[j];
+      if (r > q && r < rows && c >= q) dot += aq * a[j];
+    }
+  }
+  __syncthreads();   // pivot rows and tau_s complete
+}
+
+// S = V^T V (V with the unit diagonal, w columns) from the registers of
+// qr_regs, eight rows of S at a time; per-wave sums go through part (four
+// waves at a time), the total into S.  Overwrites a with V.
+template <int NT, int TJ>
+__device__ __forceinline__ void vtv_regs(double (&a)[TJ], int rows, int w,
+                                         double (*part)[RP][RP], double (*S)[RP + 1]) {
+  constexpr int SL = NT / 32, NW = NT / 64;
+  const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5, wave = tid >> 6;
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) {
+    const int r = slot + SL * j;
+    a[j] = (c < w && r < rows) ? (r > c ? a[j] : (r == c ? 1.0 : 0.0)) : 0.0;
+  }
+  for (int i0 = 0; i0 < RP; i0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] += shfl_col(a[j], i0 + i) * a[j];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
+    // waves 4g .. 4g + 3 add into part[0..3] in turn
+    for (int g = 0; g < NW / 4; ++g) {
+      if (wave / 4 == g && (tid & 63) < 32)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          if (g == 0) part[wave & 3][i0 + i][c] = acc[i];
+          else part[wave & 3][i0 + i][c] += acc[i];
+        }
+      if (NW > 4) __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < RP * RP; e += NT) {
+    const int i = e / RP, jj = e % RP;
+    S[i][jj] = part[0][i][jj] + part[1][i][jj] + part[2][i][jj] + part[3][i][jj];
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(256, 3)
 k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W,
             double* __restrict__ Tleaf, double* __restrict__ Stk) {
@@ -114,58 +222,7 @@ k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
     const int r = slot + 8 * j;
     a[j] = (r < rs && colok) ? a0[(int64_t)r * ld + c] : 0.0;
   }
-  if (tid < 32) tau_s[tid] = 0.0;
-  // Householder in registers, the arithmetic of qr32_factor (reflector p:
-  // v = [1; x scale], H = I - tau v v^T, a_k -= tau v (pivrow_k + scale dsum_k));
-  // the sweep that applies reflector p also forms the pivot row and the dot
-  // products of reflector p + 1
-  double dot = 0.0;
-#pragma unroll
-  for (int j = 0; j < TSJ; ++j) {
-    const int r = slot + 8 * j;
-    const double ap = shfl_col(a[j], 0);
-    if (r == 0 && colok) pivrow[0][c] = a[j];
-    if (r > 0 && r < rs) dot += ap * a[j];
-  }
-  // Every thread forms the reflector's scalars itself (the same arithmetic on
-  // the same shared values), so the two barriers of col_sum are the only
-  // ones per reflector: the sweep writes the other pivot-row buffer, and
-  // dsum and red are rewritten only after the next col_sum's first barrier,
-  // which every thread reaches after its reads of this reflector's values.
-  for (int p = 0; p < ws; ++p) {
-    col_sum<256>(dot, p, w, red, dsum);
-    const double alpha = pivrow[p & 1][p];
-    const double xnorm2 = dsum[p];
-    double beta, tau, scale;
-    if (!(xnorm2 > kQrTinyNorm2)) {
-      beta = alpha;
-      tau = 0.0;
-      scale = 0.0;
-    } else {
-      const double nrm = sqrt(alpha * alpha + xnorm2);
-      beta = (alpha >= 0.0) ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    if (tid == 0) tau_s[p] = tau;
-    const double wkc = (c > p && colok) ? pivrow[p & 1][c] + scale * dsum[c] : 0.0;
-    const int q = p + 1;
-    dot = 0.0;
-#pragma unroll
-    for (int j = 0; j < TSJ; ++j) {
-      const int r = slot + 8 * j;
-      const double ap = shfl_col(a[j], p);
-      if (r >= p && r < rs) {
-        const double vv = (r > p) ? ap * scale : 1.0;
-        if (c > p) a[j] -= tau * vv * wkc;
-        if (c == p) a[j] = (r == p) ? beta : vv;
-      }
-      const double aq = shfl_col(a[j], q & 31);
-      if (r == q && colok) pivrow[q & 1][c] = a[j];
-      if (r > q && r < rs && c >= q) dot += aq * a[j];
-    }
-  }
-  __syncthreads();   // pivot rows and tau_s complete
+  qr_regs<256, TSJ>(a, rs, w, red, dsum, pivrow, tau_s);
   // reflectors below the diagonal, R_s on and above it
 #pragma unroll
   for (int j = 0; j < TSJ; ++j) {
@@ -180,34 +237,8 @@ k_tsqr_leaf(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
     const int r = slot + 8 * j;
     if (r < RP) stk[r * RP + c] = (r < ws && colok && c >= r) ? a[j] : 0.0;
   }
-  // S = V^T V (V with the unit diagonal, ws columns), eight rows of S at a
-  // time to keep the accumulators few
-#pragma unroll
-  for (int j = 0; j < TSJ; ++j) {
-    const int r = slot + 8 * j;
-    a[j] = (c < ws && r < rs) ? (r > c ? a[j] : (r == c ? 1.0 : 0.0)) : 0.0;
-  }
-  const int wave = tid >> 6;
-  for (int i0 = 0; i0 < RP; i0 += 8) {
-    double acc[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = 0.0;
-#pragma unroll
-    for (int j = 0; j < TSJ; ++j)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] += shfl_col(a[j], i0 + i) * a[j];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], 32, 64);
-    if ((tid & 63) < 32)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) part[wave][i0 + i][c] = acc[i];
-  }
-  __syncthreads();
-  for (int e = tid; e < RP * RP; e += 256) {
-    const int i = e / RP, jj = e % RP;
-    S[i][jj] = part[0][i][jj] + part[1][i][jj] + part[2][i][jj] + part[3][i][jj];
-  }
-  __syncthreads();
+  // S = V^T V (V with the unit diagonal, ws columns)
+  vtv_regs<256, TSJ>(a, rs, ws, part, S);
   double (*Tl)[RP] = part[0];
   form_t<256>(S, tau_s, ws, Tl);
   double* Tp = Tleaf + d.leaf_off + ((int64_t)panel * d.nseg0 + sg) * RP * RP;
@@ -273,6 +304,47 @@ k_tsqr_tree(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W
     const int i = e / w, j = e % w;
     if (j >= i) W[d.w_off + (int64_t)(c0 + i) * d.n + c0 + j] = a0[i * RP + j];
   }
+}
+
+// The tree with the stack in registers (up to 32 TJ rows, TJ <= 24 doubles
+// per thread within the 128 VGPRs of a 1024-thread workgroup): the
+// arithmetic of k_tsqr_leaf
+// on 32 row slots, so that the reflectors' sweeps never leave the
+// workgroup.  Leaves the stack, tau, T_t and R as k_tsqr_tree does.
+template <int TJ>
+__global__ void __launch_bounds__(RPNT)
+k_tsqr_tree_reg(const RedDesc* __restrict__ descs, int panel, double* __restrict__ W,
+                double* __restrict__ Stk, double* __restrict__ tau, double* __restrict__ T) {
+  const RedDesc d = descs[blockIdx.x];
+  const int c0 = panel * RP;
+  if (c0 >= d.kr) return;
+  const int w = min(RP, d.kr - c0), nseg = (d.M - c0 + TS - 1) / TS, rows = nseg * RP;
+  double* a0 = Stk + d.stk_off + (int64_t)panel * d.nseg0 * RP * RP;
+  const int tid = threadIdx.x, c = tid & 31, slot = tid >> 5;
+  __shared__ double red[32][RPW];
+  __shared__ double dsum[32], pivrow[2][32], tau_s[32];
+  __shared__ double S[RP][RP + 1];
+  __shared__ double part[4][RP][RP];
+  double a[TJ];
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) {
+    const int r = slot + 32 * j;
+    a[j] = (r < rows && c < w) ? a0[r * RP + c] : 0.0;
+  }
+  qr_regs<RPNT, TJ>(a, rows, w, red, dsum, pivrow, tau_s);
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) {
+    const int r = slot + 32 * j;
+    if (r < rows && c < w) a0[r * RP + c] = a[j];
+  }
+  // the panel's R (upper triangle of the first w rows, slot r, j = 0) into W
+  if (slot < w && c < w && c >= slot) W[d.w_off + (int64_t)(c0 + slot) * d.n + c0 + c] = a[0];
+  if (tid < w) tau[d.tau_off + c0 + tid] = tau_s[tid];
+  vtv_regs<RPNT, TJ>(a, rows, w, part, S);
+  double (*Tl)[RP] = part[0];
+  form_t<RPNT>(S, tau_s, w, Tl);
+  double* Tp = T + d.t_off + (int64_t)panel * RP * RP;
+  for (int e = tid; e < RP * RP; e += RPNT) Tp[e] = Tl[e / RP][e % RP];
 }
 
 // Target of the applies: the trailing columns of W (TGT_W, op(T) = T^T:
@@ -980,7 +1052,16 @@ hipError_t launch_red_panel(const RedDesc* d, int B, int panel, int maxseg, int 
     hipLaunchKernelGGL(k_leaf_apply_mf<TGT_W>, dim3(B, (maxcols + 63) / 64, maxseg), dim3(256), 0,
                        s, d, panel, (const double*)W, (const double*)Tleaf, W);
   if (hipError_t e = hipGetLastError()) return e;
-  hipLaunchKernelGGL(k_tsqr_tree, dim3(B), dim3(RPNT), 0, s, d, panel, W, Stk, tau, T);
+  // the stack of every instance (maxseg x 32 rows at most) in registers when
+  // it fits, else swept through memory
+  if (maxseg <= 8)
+    hipLaunchKernelGGL(k_tsqr_tree_reg<8>, dim3(B), dim3(RPNT), 0, s, d, panel, W, Stk, tau, T);
+  else if (maxseg <= 16)
+    hipLaunchKernelGGL(k_tsqr_tree_reg<16>, dim3(B), dim3(RPNT), 0, s, d, panel, W, Stk, tau, T);
+  else if (maxseg <= 24)
+    hipLaunchKernelGGL(k_tsqr_tree_reg<24>, dim3(B), dim3(RPNT), 0, s, d, panel, W, Stk, tau, T);
+  else
+    hipLaunchKernelGGL(k_tsqr_tree, dim3(B), dim3(RPNT), 0, s, d, panel, W, Stk, tau, T);
   if (hipError_t e = hipGetLastError()) return e;
   if (maxcols > 0)
     hipLaunchKernelGGL(k_tree_apply_mf<TGT_W>, dim3(B, (maxcols + 63) / 64), dim3(256), 0, s, d,
