@@ -902,6 +902,18 @@ k_red_u(const RedDesc* __restrict__ descs, const InstDesc* __restrict__ sinst,
     for (int e = tid; e < G * G; e += QNT) sm[e] = og[e];
   const double* ogp = og_lds ? sm : og;
   const double* bb = beta + d.b_off;
+  __syncthreads();   // s_col, s_ni
+  // the first BREG coefficients of this thread's first (equation, rhs)
+  // pair, which every sub-chunk uses again, stay in registers
+  constexpr int BREG = 24;
+  double breg[BREG];
+  {
+    const int g = tid < P ? tid / K : 0, k = tid - g * K;
+    const int ni = tid < P ? s_ni[g] : 0;
+    const double* br = bb + (int64_t)s_col[g] * K + k;
+#pragma unroll
+    for (int q = 0; q < BREG; ++q) breg[q] = q < ni ? br[(int64_t)q * K] : 0.0;
+  }
   double* Xs = sm + (og_lds ? G * G : 0);
   const int cap = ULDS - (og_lds ? G * G : 0);
   const int ur = max(1, min(8, cap / (n + P)));
@@ -913,18 +925,17 @@ k_red_u(const RedDesc* __restrict__ descs, const InstDesc* __restrict__ sinst,
     stage_rows(Es, Y ? Y + d.v_off + (int64_t)t0 * P : nullptr, nr * P);
     __syncthreads();
     // fitted values: a thread per (equation g, rhs k) pair over the
-    // sub-chunk's rows, the block's beta column eight loads at a time
+    // sub-chunk's rows, the block's beta column eight coefficients at a time
+    // (the first pair's first BREG from registers, the rest from memory)
     for (int pq = tid; pq < P; pq += QNT) {
       const int g = pq / K, k = pq - g * K, col = s_col[g], ni = s_ni[g];
+      const bool first = pq == tid;
       const double* br = bb + (int64_t)col * K + k;
       const int* xs = sel ? sel + d.sel_off + col : nullptr;   // X column of coefficient c
       double acc[8];
 #pragma unroll
       for (int tt = 0; tt < 8; ++tt) acc[tt] = 0.0;
-      for (int c0 = 0; c0 < ni; c0 += 8) {
-        double bv[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) bv[q] = (c0 + q < ni) ? br[(int64_t)(c0 + q) * K] : 0.0;
+      auto mac = [&](const double (&bv)[8], int c0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           if (c0 + q >= ni) break;
@@ -932,18 +943,43 @@ k_red_u(const RedDesc* __restrict__ descs, const InstDesc* __restrict__ sinst,
           for (int tt = 0; tt < 8; ++tt)
             if (tt < nr) acc[tt] += Xs[tt * n + (xs ? xs[c0 + q] : col + c0 + q)] * bv[q];
         }
+      };
+#pragma unroll
+      for (int c0 = 0; c0 < BREG; c0 += 8) {
+        if (c0 < ni) {
+          double bv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            bv[q] = (c0 + q < ni) ? (first ? breg[c0 + q] : br[(int64_t)(c0 + q) * K]) : 0.0;
+          mac(bv, c0);
+        }
+      }
+      for (int c0 = BREG; c0 < ni; c0 += 8) {
+        double bv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bv[q] = (c0 + q < ni) ? br[(int64_t)(c0 + q) * K] : 0.0;
+        mac(bv, c0);
       }
 #pragma unroll
       for (int tt = 0; tt < 8; ++tt)
         if (tt < nr) Es[tt * P + pq] -= acc[tt];
     }
     __syncthreads();
+    // u = e Omega^g, four partial sums over the equations
     for (int e = tid; e < nr * P; e += QNT) {
       const int tt = e / P, rem = e - tt * P, i = rem / K, k = rem - i * K;
       const double* er = Es + tt * P + k;
-      double s = 0.0;
-      for (int g = 0; g < G; ++g) s += er[g * K] * ogp[g * G + i];
-      U[d.v_off + (int64_t)t0 * P + e] = s;
+      const double* oc = ogp + i;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int g = 0;
+      for (; g + 4 <= G; g += 4) {
+        s0 += er[g * K] * oc[g * G];
+        s1 += er[(g + 1) * K] * oc[(g + 1) * G];
+        s2 += er[(g + 2) * K] * oc[(g + 2) * G];
+        s3 += er[(g + 3) * K] * oc[(g + 3) * G];
+      }
+      for (; g < G; ++g) s0 += er[g * K] * oc[g * G];
+      U[d.v_off + (int64_t)t0 * P + e] = (s0 + s1) + (s2 + s3);
     }
   }
 }
