@@ -1,7 +1,7 @@
 // Streaming ceiling of a read/write mix: a plain kernel that moves the bytes
 // of a projection pass in the same pattern (read-only streams, streams read
 // and overwritten in place, write-only streams) with nothing else to do, so
-// that the passes' touched bandwidth can be judged against what this part
+// that the passes' touched bandwidth can be compared with what this part
 // reaches for that mix rather than against the HBM peak alone.
 //
 // Thread t of workgroup b handles the 16-byte chunks b * SU * 256 + j * 256 + t,
