@@ -191,3 +191,33 @@ def test_common_regressor_workspace_validates_the_selection():
         assert _lib.glm_workspace_bytes_common(shape, _lib.GLM_FP64, N, bad) == 0, bad
     wide = _lib.Shape([1], [50], [1], [6])
     assert _lib.glm_workspace_bytes_common(wide, _lib.GLM_FP64, [5], list(range(6))) == 0
+
+
+def test_stream_mix_refuses_bad_arguments_before_any_launch(lib):
+    """glm_stream_mix (the streaming-ceiling aid) validates its arguments on
+    the host and returns GLM_EINVAL before touching a device: the pointers
+    below are never dereferenced."""
+    from ctypes import c_int64, c_void_p
+    from paper_2510_14471_amd import _lib
+    f = lib.glm_stream_mix
+    f.argtypes = [c_void_p, c_void_p, ctypes.c_int32, c_void_p, ctypes.c_int32, c_int64,
+                  c_void_p, ctypes.c_int32, c_int64, c_void_p]
+    f.restype = ctypes.c_int
+    aligned, misaligned = 0x10000, 0x10004
+    ptrs = lambda *v: (c_void_p * len(v))(*v)            # noqa: E731
+    lens = lambda *v: (c_int64 * len(v))(*v)             # noqa: E731
+    E = _lib.GLM_EINVAL
+    # too many streams of a kind
+    assert f(ptrs(*[aligned] * 5), lens(*[64] * 5), 5, None, 0, 0, None, 0, 0, None) == E
+    assert f(None, None, 0, ptrs(*[aligned] * 5), 5, 64, None, 0, 0, None) == E
+    # misaligned, empty, or ragged read-only stream
+    assert f(ptrs(misaligned), lens(64), 1, None, 0, 0, None, 0, 0, None) == E
+    assert f(ptrs(aligned), lens(0), 1, None, 0, 0, None, 0, 0, None) == E
+    assert f(ptrs(aligned), lens(66), 1, None, 0, 0, None, 0, 0, None) == E
+    # read-write streams without a length, or ragged; write-only misaligned
+    assert f(None, None, 0, ptrs(aligned), 1, 0, None, 0, 0, None) == E
+    assert f(None, None, 0, ptrs(aligned), 1, 30, None, 0, 0, None) == E
+    assert f(None, None, 0, None, 0, 0, ptrs(misaligned), 1, 64, None) == E
+    # NULL arrays where streams are announced
+    assert f(None, None, 1, None, 0, 0, None, 0, 0, None) == E
+    assert f(None, None, 0, None, 0, 0, None, 1, 64, None) == E
