@@ -279,15 +279,20 @@ int make_plan(const glm_shape* s, glm_precision prec_flags, Plan& p, bool allow3
         const int P = in.G * in.K;
         // matrix-core passes: 64 / Gp row slots (Gp = G padded to a power of two >= 4)
         const int gp = in.G <= 4 ? 4 : in.G <= 8 ? 8 : in.G <= 16 ? 16 : in.G <= 32 ? 32 : 64;
-        const int rpar = c.gr < 0 ? 64 / gp : PROJ_NT / (P / c.kv);
+        int rpar = c.gr < 0 ? 64 / gp : PROJ_NT / (P / c.kv);
         // rows per sub-tile: the three vector slabs of pass B and the Q rows
         // must fit the stager's per-thread registers
         const int rows_v = PROJ_NVB * PROJ_NT * c.kv / (3 * P);
         const int rows_q = PROJ_NQB * PROJ_NT / n;
         int rs = std::min(std::min(rows_v, rows_q), rpar * kRowsPerLane);
-        // every row group needs a row per sub-tile; otherwise (wide Q rows,
-        // few equations) the column-slot passes stream Q better
-        if (rs < rpar) rows_fit[pi] = false;
+        // every row group needs a row per sub-tile: with wide Q rows the
+        // vector-ALU mapping keeps as many row groups as rows fit (lanes past
+        // them idle); the matrix-core mapping fixes its row groups, and
+        // without room for a single row the column-slot passes take over
+        if (rs < rpar) {
+          if (c.gr >= 0 && rs >= 1) rpar = rs;
+          else rows_fit[pi] = false;
+        }
         rs = rs / rpar * rpar;   // whole rows per row group
         in.rs_t[pi] = std::max(rs, 1);
         in.rpar_t[pi] = rpar;
